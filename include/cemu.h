@@ -1,0 +1,200 @@
+/*
+ * cemu.h -- C ABI of the MI355X (gfx950) batched TFHE gate-bootstrapping
+ * library that runs the hot path under CryptoEmu's homomorphic functional
+ * units (Gong and Negrut, "CryptoEmu: An Instruction Set Emulator for
+ * Computation Over Ciphers", arXiv 2101.03403).
+ *
+ * The paper builds every functional unit (adder, subtractor, shifters,
+ * multiplier, divider, bitwise units, Sec. 5-6) from bootstrapped binary
+ * gates of the TFHE library and names bootstrapping the dominant cost (Sec. 3,
+ * Table "TFHEbenchmark"). Its API surface -- secret/cloud keyset generation,
+ * encryption and decryption with the secret keyset, gate evaluation with the
+ * cloud keyset, and the unbootstrapped CONSTANT / NOT / COPY (Sec. 3) -- is the
+ * surface exported here, with gate evaluation batched over many gates.
+ *
+ * Conventions shared by every entry point:
+ *  - Torus elements are uint32_t (T = R/Z represented by Z/2^32, wraparound).
+ *  - An LWE ciphertext of dimension d is d+1 consecutive uint32_t words
+ *    [a_0 .. a_{d-1}, b]; batches are ciphertext-major, densely packed.
+ *  - Bits are encoded as +1/8 (true) and -1/8 (false).
+ *  - Pointers documented "device" must be device memory of the GPU on which
+ *    the cloud key was created, 4-byte aligned; "host" pointers are ordinary
+ *    host memory. All batch buffers are caller-owned; the library never frees
+ *    them and never keeps them after the call returns (device calls only
+ *    enqueue work on the caller's stream).
+ *  - Keys are opaque handles owned by the library until cemu_free_*.
+ *  - Device entry points enqueue on the given hipStream_t (passed as void*,
+ *    NULL = the default stream) and return without synchronising.
+ *  - Return value: CEMU_OK (0) or a negative cemu_status. Nothing throws or
+ *    aborts across the ABI. cemu_last_error() returns a description of the
+ *    last failure of the calling thread.
+ */
+#ifndef CEMU_H
+#define CEMU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cemu_status {
+    CEMU_OK = 0,
+    CEMU_ERR_PARAM = -1,        /* invalid or unsupported parameter value      */
+    CEMU_ERR_NULL = -2,         /* required pointer is NULL                     */
+    CEMU_ERR_ALIGN = -3,        /* pointer not 4-byte aligned                   */
+    CEMU_ERR_OOM = -4,          /* host or device allocation failed             */
+    CEMU_ERR_HIP = -5,          /* HIP runtime error                            */
+    CEMU_ERR_UNSUPPORTED = -6,  /* parameter set the kernels cannot run         */
+    CEMU_ERR_OP = -7,           /* unknown gate op code in a batch (host check) */
+    CEMU_ERR_RANGE = -8         /* index or size out of range                   */
+} cemu_status;
+
+/* Parameter sets. CEMU_STD is the standard 80-bit TFHE gate-bootstrapping set
+ * (n = 630, N = 1024, k = 1, l = 3, Bgbit = 7, t = 8, basebit = 2, LWE and
+ * key-switching noise 2^-15, bootstrapping-key noise 2^-25). CEMU_TOY is an
+ * insecure test set (n = 256, N = 512, same other values). */
+enum { CEMU_STD = 0, CEMU_TOY = 1 };
+
+/* Forms of the negacyclic polynomial products inside the blind rotation.
+ * CEMU_FORM_INT8: each key coefficient split into four signed 8-bit limbs,
+ *   products on int8 MFMA with int32 accumulation; exact modulo 2^32.
+ * CEMU_FORM_FFT64: twisted negacyclic FFT in IEEE double per product; the
+ *   result is rounded to the nearest integer and can differ from the exact
+ *   product in the low bits. */
+enum { CEMU_FORM_INT8 = 0, CEMU_FORM_FFT64 = 1 };
+
+/* Bootstrapped binary gate op codes (the ten gates of Table "TFHEbenchmark").
+ * With inputs a (first) and b (second):
+ *   NAND, AND, OR, XOR, XNOR, NOR, ANDNY = (not a) and b, ANDYN = a and (not b),
+ *   ORNY = (not a) or b, ORYN = a or (not b). */
+enum {
+    CEMU_NAND = 0, CEMU_AND = 1, CEMU_OR = 2, CEMU_XOR = 3, CEMU_XNOR = 4,
+    CEMU_NOR = 5, CEMU_ANDNY = 6, CEMU_ANDYN = 7, CEMU_ORNY = 8, CEMU_ORYN = 9,
+    CEMU_NUM_GATE_OPS = 10
+};
+
+typedef struct cemu_params {
+    int32_t n;         /* LWE dimension of gate ciphertexts                  */
+    int32_t N;         /* TRLWE ring degree: 512 or 1024                      */
+    int32_t k;         /* TRLWE mask count: must be 1                        */
+    int32_t l;         /* bootstrapping-key gadget length: must be 3          */
+    int32_t bgbit;     /* log2 gadget base: must be 7 (digits in [-64, 64))  */
+    int32_t t;         /* key-switching length: 1..16, t*basebit <= 32       */
+    int32_t basebit;   /* key-switching base bits: must be 2                  */
+    int32_t reserved;  /* set to 0                                           */
+    double sigma_lwe;  /* std dev of fresh LWE noise, torus units (>= 0)     */
+    double sigma_ks;   /* std dev of key-switching-key noise                 */
+    double sigma_bk;   /* std dev of bootstrapping-key noise                 */
+} cemu_params;
+
+typedef struct cemu_secret_key cemu_secret_key;
+typedef struct cemu_cloud_key cemu_cloud_key;
+
+/* Fill *p with a named parameter set (CEMU_STD or CEMU_TOY).
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_PARAM (unknown set). */
+int cemu_params_default(cemu_params *p, int which);
+
+/* Secret-keyset and cloud-keyset generation (Sec. 3, "TFHE API": keyset
+ * generation precedes all gate evaluation). Deterministic in seed: every
+ * random value is a Philox4x32-10 output at a fixed counter, keyed by seed,
+ * so the same seed gives the same keys on any machine. The secret key stays
+ * on the host. The cloud key (bootstrapping key in the int8-limb layout and
+ * the key-switching key) is uploaded to the current HIP device; the FFT form
+ * of the bootstrapping key is built on that device on first use.
+ * Ownership: *sk and *ck are owned by the library until cemu_free_*.
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_PARAM / CEMU_ERR_UNSUPPORTED (parameter set
+ * outside the limits stated in cemu_params), CEMU_ERR_OOM, CEMU_ERR_HIP. */
+int cemu_keygen(const cemu_params *p, uint64_t seed, cemu_secret_key **sk, cemu_cloud_key **ck);
+
+/* Copy the parameters of a key. */
+int cemu_secret_params(const cemu_secret_key *sk, cemu_params *p);
+int cemu_cloud_params(const cemu_cloud_key *ck, cemu_params *p);
+
+/* Encrypt (Sec. 3, Table "TFHEbenchmark": Encrypt). bits: host [count]
+ * (0 = false, nonzero = true). out: host [count][n+1]. Ciphertext e uses the
+ * encryption stream (seed, first_index + e), so a batch can be produced in
+ * pieces. Errors: CEMU_ERR_NULL, CEMU_ERR_RANGE (count < 0). */
+int cemu_encrypt(const cemu_secret_key *sk, const uint8_t *bits, int64_t count, uint64_t seed,
+                 uint64_t first_index, uint32_t *out);
+
+/* Decrypt (Table "TFHEbenchmark": Decrypt): bit = (phase as int32) > 0.
+ * ct: host [count][n+1]; bits: host [count].
+ * cemu_decrypt_extracted takes dimension-N samples [count][N+1] (the output
+ * of cemu_blind_rotate_extract), decrypted with the TRLWE key coefficients.
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_RANGE. */
+int cemu_decrypt(const cemu_secret_key *sk, const uint32_t *ct, int64_t count, uint8_t *bits);
+int cemu_decrypt_extracted(const cemu_secret_key *sk, const uint32_t *ct, int64_t count, uint8_t *bits);
+
+/* Phase b - <a, s> of each ciphertext, for noise measurement. extracted = 0:
+ * ct is [count][n+1] under the LWE key; extracted = 1: [count][N+1] under the
+ * TRLWE key coefficients. phase: host [count]. */
+int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int64_t count, uint32_t *phase);
+
+/* Batched bootstrapped binary gates: lincomb + modulus switch + blind
+ * rotation + sample extraction + key switching, for B independent gates.
+ *   ops:      device uint8_t [B], gate op codes (CEMU_NAND .. CEMU_ORYN)
+ *   pool_in:  device uint32_t [P_in][n+1], ciphertext pool read by the gates
+ *   ia, ib:   device int32_t [B], row of the first / second input in pool_in
+ *   io:       device int32_t [B], row of pool_out receiving gate g's output;
+ *             NULL means row g
+ *   pool_out: device uint32_t [P_out][n+1]; may alias pool_in only if no
+ *             output row is also an input row of this batch
+ * Row indices are not range-checked on the device: the caller guarantees
+ * 0 <= ia, ib < P_in and io (or g) < P_out, and unknown op codes produce an
+ * unspecified ciphertext. B = 0 is a no-op. Scratch: the library keeps
+ * per-cloud-key device workspaces sized for the largest B seen (allocated on
+ * demand, so this call may allocate). Calls sharing one cloud key must not
+ * overlap in time on different streams.
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0),
+ * CEMU_ERR_PARAM (unknown form), CEMU_ERR_OOM, CEMU_ERR_HIP. */
+int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
+                         const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out,
+                         int64_t B, void *hip_stream);
+
+/* The same gates without the final key switch: writes the extracted
+ * dimension-N samples. out_N: device uint32_t [B][N+1]. */
+int cemu_blind_rotate_extract(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
+                              const int32_t *ia, const int32_t *ib, uint32_t *out_N, int64_t B,
+                              void *hip_stream);
+
+/* Key switching of B dimension-N samples to dimension n.
+ * in_N: device [B][N+1]; out_n: device [B][n+1]. */
+int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *out_n, int64_t B,
+                    void *hip_stream);
+
+/* Unbootstrapped operations of Table "TFHEbenchmark" on a device pool
+ * [P][n+1]: NOT (negation of every word), COPY, and CONSTANT (trivial
+ * ciphertext (0,...,0, +-1/8)). src, dst: device int32_t [count] rows; for
+ * constant, bits is device uint8_t [count]. No key material is needed, only
+ * the dimension n. */
+int cemu_lwe_not(int32_t n, const uint32_t *pool_in, const int32_t *src, uint32_t *pool_out,
+                 const int32_t *dst, int64_t count, void *hip_stream);
+int cemu_lwe_copy(int32_t n, const uint32_t *pool_in, const int32_t *src, uint32_t *pool_out,
+                  const int32_t *dst, int64_t count, void *hip_stream);
+int cemu_lwe_constant(int32_t n, const uint8_t *bits, uint32_t *pool_out, const int32_t *dst, int64_t count,
+                      void *hip_stream);
+
+/* Export all key material in the canonical Torus32 layout (host buffers, each
+ * may be NULL to skip): lwe_key int32 [n]; tlwe_key int32 [N];
+ * bk uint32 [n][2l][2][N] (row c*l+j, component A then B);
+ * ksk uint32 [N][t][2^basebit][n+1]. The bootstrapping key is read back from
+ * the device (and its int8 limbs recombined), so the export checks the
+ * uploaded key. */
+int cemu_export_keys(const cemu_secret_key *sk, const cemu_cloud_key *ck, int32_t *lwe_key, int32_t *tlwe_key,
+                     uint32_t *bk, uint32_t *ksk);
+
+void cemu_free_secret_key(cemu_secret_key *sk);
+void cemu_free_cloud_key(cemu_cloud_key *ck);
+
+/* Description of the calling thread's last error ("" if none). */
+const char *cemu_last_error(void);
+
+/* Library version string. */
+const char *cemu_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CEMU_H */

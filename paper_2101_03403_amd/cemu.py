@@ -1,0 +1,242 @@
+"""Python binding of libcemu (argument marshalling only).
+
+Every step of gate bootstrapping runs in the HIP kernels of ``libcemu.so``;
+this module only converts arguments and checks return codes. Device buffers
+are torch tensors on the GPU that holds the cloud key; torch is used for
+device memory and streams only. Torus32 words are carried in ``torch.int32``
+tensors (same bits as uint32).
+
+The library must be built (``python -m paper_2101_03403_amd.build``); there is
+no fallback: if ``libcemu.so`` is missing, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcemu.so")
+
+STD, TOY = 0, 1
+FORM_INT8, FORM_FFT64 = 0, 1
+FORMS = {"int8": FORM_INT8, "fft64": FORM_FFT64}
+
+NAND, AND, OR, XOR, XNOR, NOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
+GATE_NAMES = ["NAND", "AND", "OR", "XOR", "XNOR", "NOR", "ANDNY", "ANDYN", "ORNY", "ORYN"]
+
+TRUE_T32 = 0x20000000
+FALSE_T32 = 0xE0000000
+
+
+class CemuError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cemu error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("n", C.c_int32), ("N", C.c_int32), ("k", C.c_int32), ("l", C.c_int32),
+                ("bgbit", C.c_int32), ("t", C.c_int32), ("basebit", C.c_int32), ("reserved", C.c_int32),
+                ("sigma_lwe", C.c_double), ("sigma_ks", C.c_double), ("sigma_bk", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
+EXPORTED = [
+    "cemu_params_default", "cemu_keygen", "cemu_secret_params", "cemu_cloud_params", "cemu_encrypt",
+    "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates",
+    "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
+    "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
+]
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libcemu.so (raises FileNotFoundError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FileNotFoundError(f"{LIB_PATH} is missing: build it with `python -m paper_2101_03403_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+    pp = C.POINTER(Params)
+    L.cemu_params_default.argtypes = [pp, C.c_int]
+    L.cemu_keygen.argtypes = [pp, C.c_uint64, C.POINTER(vp), C.POINTER(vp)]
+    L.cemu_secret_params.argtypes = [vp, pp]
+    L.cemu_cloud_params.argtypes = [vp, pp]
+    L.cemu_encrypt.argtypes = [vp, vp, i64, C.c_uint64, C.c_uint64, vp]
+    L.cemu_decrypt.argtypes = [vp, vp, i64, vp]
+    L.cemu_decrypt_extracted.argtypes = [vp, vp, i64, vp]
+    L.cemu_phase.argtypes = [vp, C.c_int, vp, i64, vp]
+    L.cemu_bootstrap_gates.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.cemu_blind_rotate_extract.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp]
+    L.cemu_key_switch.argtypes = [vp, vp, vp, i64, vp]
+    L.cemu_lwe_not.argtypes = [i32, vp, vp, vp, vp, i64, vp]
+    L.cemu_lwe_copy.argtypes = [i32, vp, vp, vp, vp, i64, vp]
+    L.cemu_lwe_constant.argtypes = [i32, vp, vp, vp, i64, vp]
+    L.cemu_export_keys.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.cemu_free_secret_key.argtypes = [vp]
+    L.cemu_free_secret_key.restype = None
+    L.cemu_free_cloud_key.argtypes = [vp]
+    L.cemu_free_cloud_key.restype = None
+    L.cemu_last_error.restype = C.c_char_p
+    L.cemu_version.restype = C.c_char_p
+    for name in EXPORTED:
+        getattr(L, name)  # raises AttributeError if a declared entry point is missing
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise CemuError(rc, lib().cemu_last_error().decode())
+
+
+def params(which=STD, **overrides) -> Params:
+    p = Params()
+    _check(lib().cemu_params_default(C.byref(p), int(which)))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _np_ptr(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+@dataclass
+class Keys:
+    """Secret key (host) and cloud key (device) handles."""
+    sk: C.c_void_p
+    ck: C.c_void_p
+    params: Params
+
+    @property
+    def n(self) -> int:
+        return self.params.n
+
+    @property
+    def N(self) -> int:
+        return self.params.N
+
+    def free(self):
+        if self.sk:
+            lib().cemu_free_secret_key(self.sk)
+            self.sk = None
+        if self.ck:
+            lib().cemu_free_cloud_key(self.ck)
+            self.ck = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- host side
+    def encrypt(self, bits, seed: int, first_index: int = 0) -> np.ndarray:
+        bits = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
+        out = np.zeros((bits.shape[0], self.n + 1), np.uint32)
+        _check(lib().cemu_encrypt(self.sk, _np_ptr(bits), bits.shape[0], seed, first_index, _np_ptr(out)))
+        return out
+
+    def decrypt(self, cts) -> np.ndarray:
+        cts = np.ascontiguousarray(np.asarray(cts).view(np.uint32).reshape(-1, self.n + 1))
+        out = np.zeros(cts.shape[0], np.uint8)
+        _check(lib().cemu_decrypt(self.sk, _np_ptr(cts), cts.shape[0], _np_ptr(out)))
+        return out
+
+    def decrypt_extracted(self, cts) -> np.ndarray:
+        cts = np.ascontiguousarray(np.asarray(cts).view(np.uint32).reshape(-1, self.N + 1))
+        out = np.zeros(cts.shape[0], np.uint8)
+        _check(lib().cemu_decrypt_extracted(self.sk, _np_ptr(cts), cts.shape[0], _np_ptr(out)))
+        return out
+
+    def phase(self, cts, extracted: bool = False) -> np.ndarray:
+        d = self.N if extracted else self.n
+        cts = np.ascontiguousarray(np.asarray(cts).view(np.uint32).reshape(-1, d + 1))
+        out = np.zeros(cts.shape[0], np.uint32)
+        _check(lib().cemu_phase(self.sk, int(extracted), _np_ptr(cts), cts.shape[0], _np_ptr(out)))
+        return out
+
+    def export(self, bk: bool = True, ksk: bool = True) -> dict:
+        p = self.params
+        lwe = np.zeros(p.n, np.int32)
+        tlwe = np.zeros(p.N, np.int32)
+        bka = np.zeros((p.n, 2 * p.l, 2, p.N), np.uint32) if bk else None
+        ksa = np.zeros((p.N, p.t, 1 << p.basebit, p.n + 1), np.uint32) if ksk else None
+        _check(lib().cemu_export_keys(self.sk, self.ck, _np_ptr(lwe), _np_ptr(tlwe),
+                                      _np_ptr(bka) if bk else None, _np_ptr(ksa) if ksk else None))
+        return {"lwe_key": lwe, "tlwe_key": tlwe, "bk": bka, "ksk": ksa}
+
+
+def keygen(p=STD, seed: int = 0) -> Keys:
+    """Generate keys; the cloud key goes to the current torch/HIP device."""
+    if not isinstance(p, Params):
+        p = params(p)
+    sk, ck = C.c_void_p(), C.c_void_p()
+    _check(lib().cemu_keygen(C.byref(p), seed, C.byref(sk), C.byref(ck)))
+    return Keys(sk, ck, p)
+
+
+# ------------------------------------------------------------------ device side
+def bootstrap_gates(keys: Keys, ops, pool_in, ia, ib, pool_out, io=None, form="int8", stream=None):
+    """Batched bootstrapped gates; see cemu_bootstrap_gates in include/cemu.h."""
+    B = int(ops.shape[0])
+    _check(lib().cemu_bootstrap_gates(keys.ck, FORMS[form], _dptr(ops), _dptr(pool_in), _dptr(ia), _dptr(ib),
+                                      _dptr(io), _dptr(pool_out), B, _stream(stream)))
+
+
+def blind_rotate_extract(keys: Keys, ops, pool_in, ia, ib, out_N, form="int8", stream=None):
+    B = int(ops.shape[0])
+    _check(lib().cemu_blind_rotate_extract(keys.ck, FORMS[form], _dptr(ops), _dptr(pool_in), _dptr(ia), _dptr(ib),
+                                           _dptr(out_N), B, _stream(stream)))
+
+
+def key_switch(keys: Keys, in_N, out_n, stream=None):
+    B = int(in_N.shape[0])
+    _check(lib().cemu_key_switch(keys.ck, _dptr(in_N), _dptr(out_n), B, _stream(stream)))
+
+
+def lwe_not(n: int, pool_in, src, pool_out, dst, stream=None):
+    _check(lib().cemu_lwe_not(n, _dptr(pool_in), _dptr(src), _dptr(pool_out), _dptr(dst), int(src.shape[0]),
+                              _stream(stream)))
+
+
+def lwe_copy(n: int, pool_in, src, pool_out, dst, stream=None):
+    _check(lib().cemu_lwe_copy(n, _dptr(pool_in), _dptr(src), _dptr(pool_out), _dptr(dst), int(src.shape[0]),
+                               _stream(stream)))
+
+
+def lwe_constant(n: int, bits, pool_out, dst, stream=None):
+    _check(lib().cemu_lwe_constant(n, _dptr(bits), _dptr(pool_out), _dptr(dst), int(dst.shape[0]),
+                                   _stream(stream)))
+
+
+def version() -> str:
+    return lib().cemu_version().decode()

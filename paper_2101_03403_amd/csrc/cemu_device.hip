@@ -1,0 +1,402 @@
+// Device part of libcemu for gfx950 (MI355X): key upload, the gate
+// linear-combination + modulus-switch kernel, the blind-rotation kernels
+// (int8-MFMA form in cemu_br_int8.hip, FFT64 form in cemu_br_fft.hip), the
+// key-switching kernel, the unbootstrapped NOT / COPY / CONSTANT kernels, and
+// the device entry points of the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "cemu_internal.h"
+#include "cemu_kernels.h"
+
+namespace cemu {
+
+namespace {
+
+std::string hip_msg(const char *what, hipError_t e)
+{
+    return std::string(what) + ": " + hipGetErrorString(e);
+}
+
+#define CEMU_HIP(call)                                                   \
+    do {                                                                 \
+        hipError_t e_ = (call);                                          \
+        if (e_ != hipSuccess) return fail(CEMU_ERR_HIP, hip_msg(#call, e_)); \
+    } while (0)
+
+// Gate constants: (kappa, w1, w2) with c = (0,...,0,kappa) + w1*c1 + w2*c2.
+// Encoding +-1/8 for bits; the gate set of Table "TFHEbenchmark".
+__constant__ uint32_t c_gate_kappa[CEMU_NUM_GATE_OPS] = {
+    0x20000000u, 0xE0000000u, 0x20000000u, 0x40000000u, 0xC0000000u,
+    0xE0000000u, 0xE0000000u, 0xE0000000u, 0x20000000u, 0x20000000u};
+__constant__ int32_t c_gate_w1[CEMU_NUM_GATE_OPS] = {-1, 1, 1, 2, -2, -1, -1, 1, -1, 1};
+__constant__ int32_t c_gate_w2[CEMU_NUM_GATE_OPS] = {-1, 1, 1, 2, -2, -1, 1, -1, 1, -1};
+
+// K1: gate linear combination fused with the modulus switch to Z/2N.
+// One thread per (gate, coefficient); bars is [B][n+1] u16 row-major.
+__global__ void lincomb_modswitch_kernel(const uint8_t *__restrict__ ops, const uint32_t *__restrict__ pool,
+                                         const int32_t *__restrict__ ia, const int32_t *__restrict__ ib,
+                                         int32_t n, int32_t log2_2n, int64_t B, uint16_t *__restrict__ bars)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = n + 1;
+    if (idx >= B * row) return;
+    const int64_t g = idx / row;
+    const int32_t u = (int32_t)(idx - g * row);
+    uint32_t op = ops[g];
+    if (op >= CEMU_NUM_GATE_OPS) op = 0;
+    const uint32_t x1 = pool[(int64_t)ia[g] * row + u];
+    const uint32_t x2 = pool[(int64_t)ib[g] * row + u];
+    uint32_t x = (uint32_t)c_gate_w1[op] * x1 + (uint32_t)c_gate_w2[op] * x2;
+    if (u == n) x += c_gate_kappa[op];
+    // nearest integer to x * 2N / 2^32, mod 2N (the shift drops the wrap)
+    const uint32_t half = 1u << (31 - log2_2n);
+    bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
+}
+
+// K3: key switching N -> n. A workgroup takes KS_G samples; thread t owns
+// output columns t, t+256, t+512 for all of them. The rounded inputs are
+// staged in LDS; each key row is read once per workgroup and applied to the
+// KS_G samples from registers.
+constexpr int KS_G = 16;
+constexpr int KS_THREADS = 256;
+constexpr int KS_COLS = 3;   // 3 * 256 >= n + 1 for n <= 767
+
+template <int N>
+__global__ __launch_bounds__(KS_THREADS) void key_switch_kernel(const uint32_t *__restrict__ ext,
+                                                                const uint32_t *__restrict__ ksk, int32_t n,
+                                                                int32_t t, int64_t B, const int32_t *__restrict__ io,
+                                                                uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t xr[KS_G][N];
+    __shared__ uint32_t bprime[KS_G];
+    const int tid = threadIdx.x;
+    const int64_t g0 = (int64_t)blockIdx.x * KS_G;
+    const int prec = 2 * t;                       // basebit = 2
+    const uint32_t round = prec >= 32 ? 0u : (1u << (31 - prec));
+    for (int e = tid; e < KS_G * N; e += KS_THREADS) {
+        const int g = e / N, i = e - g * N;
+        uint32_t v = 0;
+        if (g0 + g < B) {
+            const uint32_t a = ext[(g0 + g) * (N + 1) + i];
+            v = prec >= 32 ? a : ((a + round) >> (32 - prec));
+        }
+        xr[g][i] = v;
+    }
+    if (tid < KS_G) bprime[tid] = (g0 + tid < B) ? ext[(g0 + tid) * (N + 1) + N] : 0u;
+    __syncthreads();
+
+    const int64_t rowlen = n + 1;
+    uint32_t acc[KS_G][KS_COLS];
+#pragma unroll
+    for (int g = 0; g < KS_G; ++g)
+#pragma unroll
+        for (int c = 0; c < KS_COLS; ++c) acc[g][c] = 0u;
+    int col[KS_COLS];
+    bool ok[KS_COLS];
+#pragma unroll
+    for (int c = 0; c < KS_COLS; ++c) {
+        col[c] = tid + c * KS_THREADS;
+        ok[c] = col[c] <= n;
+        if (!ok[c]) col[c] = n;  // keep loads in bounds; result discarded
+    }
+    for (int i = 0; i < N; ++i) {
+        for (int j = 0; j < t; ++j) {
+            const uint32_t *rows = ksk + ((int64_t)i * t + j) * 4 * rowlen;
+            uint32_t r1[KS_COLS], r2[KS_COLS], r3[KS_COLS];
+#pragma unroll
+            for (int c = 0; c < KS_COLS; ++c) {
+                r1[c] = rows[rowlen + col[c]];
+                r2[c] = rows[2 * rowlen + col[c]];
+                r3[c] = rows[3 * rowlen + col[c]];
+            }
+            const int sh = prec - 2 * (j + 1);
+#pragma unroll
+            for (int g = 0; g < KS_G; ++g) {
+                const uint32_t d = (xr[g][i] >> sh) & 3u;
+#pragma unroll
+                for (int c = 0; c < KS_COLS; ++c) {
+                    const uint32_t v = d == 1u ? r1[c] : (d == 2u ? r2[c] : (d == 3u ? r3[c] : 0u));
+                    acc[g][c] -= v;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < KS_G; ++g) {
+        if (g0 + g >= B) break;
+        const int64_t orow = io ? (int64_t)io[g0 + g] : g0 + g;
+#pragma unroll
+        for (int c = 0; c < KS_COLS; ++c) {
+            if (!ok[c]) continue;
+            uint32_t v = acc[g][c];
+            if (col[c] == n) v += bprime[g];
+            out[orow * rowlen + col[c]] = v;
+        }
+    }
+}
+
+__global__ void lwe_not_kernel(int32_t n, const uint32_t *__restrict__ in, const int32_t *__restrict__ src,
+                               uint32_t *__restrict__ out, const int32_t *__restrict__ dst, int64_t count)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = n + 1;
+    if (idx >= count * row) return;
+    const int64_t e = idx / row, u = idx - e * row;
+    out[(int64_t)dst[e] * row + u] = 0u - in[(int64_t)src[e] * row + u];
+}
+
+__global__ void lwe_copy_kernel(int32_t n, const uint32_t *__restrict__ in, const int32_t *__restrict__ src,
+                                uint32_t *__restrict__ out, const int32_t *__restrict__ dst, int64_t count)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = n + 1;
+    if (idx >= count * row) return;
+    const int64_t e = idx / row, u = idx - e * row;
+    out[(int64_t)dst[e] * row + u] = in[(int64_t)src[e] * row + u];
+}
+
+__global__ void lwe_constant_kernel(int32_t n, const uint8_t *__restrict__ bits, uint32_t *__restrict__ out,
+                                    const int32_t *__restrict__ dst, int64_t count)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = n + 1;
+    if (idx >= count * row) return;
+    const int64_t e = idx / row, u = idx - e * row;
+    out[(int64_t)dst[e] * row + u] = u == n ? (bits[e] ? 0x20000000u : 0xE0000000u) : 0u;
+}
+
+inline bool misaligned(const void *p) { return ((uintptr_t)p & 3u) != 0; }
+
+int ensure_workspace(cemu_cloud_key *ck, int64_t B, bool need_ext)
+{
+    const int32_t n = ck->p.n, N = ck->p.N;
+    if (ck->bars_cap < B) {
+        if (ck->d_bars) CEMU_HIP(hipFree(ck->d_bars));
+        ck->d_bars = nullptr;
+        ck->bars_cap = 0;
+        if (hipMalloc(&ck->d_bars, (size_t)B * (n + 1) * sizeof(uint16_t)) != hipSuccess)
+            return fail(CEMU_ERR_OOM, "device workspace allocation failed");
+        ck->bars_cap = B;
+    }
+    if (need_ext && ck->ext_cap < B) {
+        if (ck->d_ext) CEMU_HIP(hipFree(ck->d_ext));
+        ck->d_ext = nullptr;
+        ck->ext_cap = 0;
+        if (hipMalloc(&ck->d_ext, (size_t)B * (N + 1) * sizeof(uint32_t)) != hipSuccess)
+            return fail(CEMU_ERR_OOM, "device workspace allocation failed");
+        ck->ext_cap = B;
+    }
+    return CEMU_OK;
+}
+
+int log2_of(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+int launch_lincomb(const cemu_cloud_key *ck, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
+                   const int32_t *ib, int64_t B, hipStream_t s)
+{
+    const int32_t n = ck->p.n;
+    const int64_t total = B * (n + 1);
+    const int threads = 256;
+    const int64_t blocks = (total + threads - 1) / threads;
+    hipLaunchKernelGGL(lincomb_modswitch_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, ops, pool, ia, ib, n,
+                       log2_of(2 * ck->p.N), B, ck->d_bars);
+    CEMU_HIP(hipGetLastError());
+    return CEMU_OK;
+}
+
+int launch_key_switch(const cemu_cloud_key *ck, const uint32_t *ext, const int32_t *io, uint32_t *out, int64_t B,
+                      hipStream_t s)
+{
+    const int32_t n = ck->p.n, N = ck->p.N, t = ck->p.t;
+    if (n + 1 > KS_COLS * KS_THREADS) return fail(CEMU_ERR_UNSUPPORTED, "key switch supports n <= 767");
+    const int64_t blocks = (B + KS_G - 1) / KS_G;
+    if (N == 1024)
+        hipLaunchKernelGGL(key_switch_kernel<1024>, dim3((unsigned)blocks), dim3(KS_THREADS), 0, s, ext, ck->d_ksk, n,
+                           t, B, io, out);
+    else
+        hipLaunchKernelGGL(key_switch_kernel<512>, dim3((unsigned)blocks), dim3(KS_THREADS), 0, s, ext, ck->d_ksk, n,
+                           t, B, io, out);
+    CEMU_HIP(hipGetLastError());
+    return CEMU_OK;
+}
+
+int check_device(const cemu_cloud_key *ck)
+{
+    int dev = -1;
+    CEMU_HIP(hipGetDevice(&dev));
+    if (dev != ck->device) return fail(CEMU_ERR_PARAM, "current HIP device differs from the cloud key's device");
+    return CEMU_OK;
+}
+
+// Lincomb + blind rotation + extraction into ext_out ([B][N+1]).
+int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
+                     const int32_t *ib, uint32_t *ext_out, int64_t B, hipStream_t s)
+{
+    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, s);
+    if (rc) return rc;
+    if (form == CEMU_FORM_INT8) return launch_br_int8(ck, ck->d_bars, B, ext_out, s);
+    if (form == CEMU_FORM_FFT64) return launch_br_fft(ck, ck->d_bars, B, ext_out, s);
+    return fail(CEMU_ERR_PARAM, "unknown product form");
+}
+
+}  // namespace
+
+int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const std::vector<uint32_t> &ksk)
+{
+    CEMU_HIP(hipGetDevice(&ck->device));
+    if (hipMalloc(&ck->d_bk8, bk8.size()) != hipSuccess) return fail(CEMU_ERR_OOM, "device allocation (BK) failed");
+    if (hipMalloc(&ck->d_ksk, ksk.size() * sizeof(uint32_t)) != hipSuccess) {
+        release_cloud_key(ck);
+        return fail(CEMU_ERR_OOM, "device allocation (KSK) failed");
+    }
+    hipError_t e1 = hipMemcpy(ck->d_bk8, bk8.data(), bk8.size(), hipMemcpyHostToDevice);
+    hipError_t e2 = hipMemcpy(ck->d_ksk, ksk.data(), ksk.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess) {
+        release_cloud_key(ck);
+        return fail(CEMU_ERR_HIP, hip_msg("hipMemcpy (key upload)", e1 != hipSuccess ? e1 : e2));
+    }
+    return CEMU_OK;
+}
+
+int download_bk8(const cemu_cloud_key *ck, std::vector<uint8_t> &bk8)
+{
+    const cemu_params &p = ck->p;
+    bk8.resize((size_t)p.n * 2 * p.l * 2 * 4 * 2 * p.N);
+    CEMU_HIP(hipMemcpy(bk8.data(), ck->d_bk8, bk8.size(), hipMemcpyDeviceToHost));
+    return CEMU_OK;
+}
+
+int download_ksk(const cemu_cloud_key *ck, std::vector<uint32_t> &ksk)
+{
+    const cemu_params &p = ck->p;
+    ksk.resize((size_t)p.N * p.t * (1 << p.basebit) * (p.n + 1));
+    CEMU_HIP(hipMemcpy(ksk.data(), ck->d_ksk, ksk.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return CEMU_OK;
+}
+
+void release_cloud_key(cemu_cloud_key *ck)
+{
+    if (ck->d_bk8) (void)hipFree(ck->d_bk8);
+    if (ck->d_ksk) (void)hipFree(ck->d_ksk);
+    if (ck->d_bkfft) (void)hipFree(ck->d_bkfft);
+    if (ck->d_bars) (void)hipFree(ck->d_bars);
+    if (ck->d_ext) (void)hipFree(ck->d_ext);
+    ck->d_bk8 = nullptr;
+    ck->d_ksk = nullptr;
+    ck->d_bkfft = nullptr;
+    ck->d_bars = nullptr;
+    ck->d_ext = nullptr;
+    ck->bars_cap = ck->ext_cap = 0;
+}
+
+}  // namespace cemu
+
+using namespace cemu;
+
+extern "C" {
+
+int cemu_bootstrap_gates(const cemu_cloud_key *ckc, int form, const uint8_t *ops, const uint32_t *pool_in,
+                         const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out, int64_t B,
+                         void *hip_stream)
+{
+    clear_error();
+    if (!ckc) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
+    if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
+    if (B == 0) return CEMU_OK;
+    if (!ops || !pool_in || !ia || !ib || !pool_out) return fail(CEMU_ERR_NULL, "NULL device buffer");
+    if (misaligned(pool_in) || misaligned(ia) || misaligned(ib) || misaligned(pool_out) || (io && misaligned(io)))
+        return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    cemu_cloud_key *ck = const_cast<cemu_cloud_key *>(ckc);
+    std::lock_guard<std::mutex> lock(ck->mu);
+    int rc = check_device(ck);
+    if (rc) return rc;
+    rc = ensure_workspace(ck, B, true);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)hip_stream;
+    rc = run_blind_rotate(ck, form, ops, pool_in, ia, ib, ck->d_ext, B, s);
+    if (rc) return rc;
+    return launch_key_switch(ck, ck->d_ext, io, pool_out, B, s);
+}
+
+int cemu_blind_rotate_extract(const cemu_cloud_key *ckc, int form, const uint8_t *ops, const uint32_t *pool_in,
+                              const int32_t *ia, const int32_t *ib, uint32_t *out_N, int64_t B, void *hip_stream)
+{
+    clear_error();
+    if (!ckc) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
+    if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
+    if (B == 0) return CEMU_OK;
+    if (!ops || !pool_in || !ia || !ib || !out_N) return fail(CEMU_ERR_NULL, "NULL device buffer");
+    if (misaligned(pool_in) || misaligned(ia) || misaligned(ib) || misaligned(out_N))
+        return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    cemu_cloud_key *ck = const_cast<cemu_cloud_key *>(ckc);
+    std::lock_guard<std::mutex> lock(ck->mu);
+    int rc = check_device(ck);
+    if (rc) return rc;
+    rc = ensure_workspace(ck, B, false);
+    if (rc) return rc;
+    return run_blind_rotate(ck, form, ops, pool_in, ia, ib, out_N, B, (hipStream_t)hip_stream);
+}
+
+int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *out_n, int64_t B, void *hip_stream)
+{
+    clear_error();
+    if (!ck) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
+    if (B == 0) return CEMU_OK;
+    if (!in_N || !out_n) return fail(CEMU_ERR_NULL, "NULL device buffer");
+    if (misaligned(in_N) || misaligned(out_n)) return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    int rc = check_device(ck);
+    if (rc) return rc;
+    return launch_key_switch(ck, in_N, nullptr, out_n, B, (hipStream_t)hip_stream);
+}
+
+static int launch_rowwise(int which, int32_t n, const uint32_t *in, const int32_t *src, const uint8_t *bits,
+                          uint32_t *out, const int32_t *dst, int64_t count, void *hip_stream)
+{
+    clear_error();
+    if (count < 0) return fail(CEMU_ERR_RANGE, "count < 0");
+    if (n < 1) return fail(CEMU_ERR_PARAM, "n must be >= 1");
+    if (count == 0) return CEMU_OK;
+    if (!out || !dst || (which < 2 && (!in || !src)) || (which == 2 && !bits))
+        return fail(CEMU_ERR_NULL, "NULL device buffer");
+    const int64_t total = count * (n + 1);
+    const int threads = 256;
+    const dim3 grid((unsigned)((total + threads - 1) / threads));
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (which == 0) hipLaunchKernelGGL(lwe_not_kernel, grid, dim3(threads), 0, s, n, in, src, out, dst, count);
+    else if (which == 1) hipLaunchKernelGGL(lwe_copy_kernel, grid, dim3(threads), 0, s, n, in, src, out, dst, count);
+    else hipLaunchKernelGGL(lwe_constant_kernel, grid, dim3(threads), 0, s, n, bits, out, dst, count);
+    CEMU_HIP(hipGetLastError());
+    return CEMU_OK;
+}
+
+int cemu_lwe_not(int32_t n, const uint32_t *pool_in, const int32_t *src, uint32_t *pool_out, const int32_t *dst,
+                 int64_t count, void *hip_stream)
+{
+    return launch_rowwise(0, n, pool_in, src, nullptr, pool_out, dst, count, hip_stream);
+}
+
+int cemu_lwe_copy(int32_t n, const uint32_t *pool_in, const int32_t *src, uint32_t *pool_out, const int32_t *dst,
+                  int64_t count, void *hip_stream)
+{
+    return launch_rowwise(1, n, pool_in, src, nullptr, pool_out, dst, count, hip_stream);
+}
+
+int cemu_lwe_constant(int32_t n, const uint8_t *bits, uint32_t *pool_out, const int32_t *dst, int64_t count,
+                      void *hip_stream)
+{
+    return launch_rowwise(2, n, nullptr, nullptr, bits, pool_out, dst, count, hip_stream);
+}
+
+}  // extern "C"

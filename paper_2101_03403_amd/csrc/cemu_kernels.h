@@ -1,0 +1,16 @@
+// Launchers of the blind-rotation kernels (one translation unit per form).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cemu_internal.h"
+
+namespace cemu {
+
+// Blind rotation + sample extraction for B mod-switched samples.
+//   bars: device u16 [B][n+1] (abar_0 .. abar_{n-1}, bbar), values in [0, 2N)
+//   ext:  device u32 [B][N+1] extracted samples
+int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
+int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
+
+}  // namespace cemu

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Keys are generated independently on both sides from the same seed (library
+host code vs. oracle, each implementing Philox4x32-10 and Box-Muller), so the
+first tests check key and encryption parity bit for bit. The int8-MFMA form
+must then give bit-identical extracted samples and key-switched outputs.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_2101_03403_amd import cemu, workloads as W  # noqa: E402
+
+SEED = 20210108
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def toy(dev):
+    say("[gpu] keygen toy (library + oracle)")
+    return cemu.keygen(cemu.TOY, SEED), O.keygen(O.TOY, SEED)
+
+
+@pytest.fixture(scope="module")
+def std(dev):
+    say("[gpu] keygen std (library + oracle)")
+    return cemu.keygen(cemu.STD, SEED), O.keygen(O.STANDARD, SEED)
+
+
+def to_dev(a, dev):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint32:
+        a = a.view(np.int32)
+    return torch.from_numpy(a).to(dev)
+
+
+def to_host_u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def run_gates(keys, ops, c1, c2, dev, form="int8", want_ext=True):
+    """Pool = [c1; c2]; gate g reads rows g and B+g. Returns (ext, out)."""
+    B = ops.shape[0]
+    pool = to_dev(np.concatenate([c1, c2]), dev)
+    ops_t = torch.from_numpy(np.ascontiguousarray(ops.astype(np.uint8))).to(dev)
+    ia = torch.arange(B, dtype=torch.int32, device=dev)
+    ib = ia + B
+    out = torch.zeros((B, keys.n + 1), dtype=torch.int32, device=dev)
+    ext = None
+    if want_ext:
+        ext = torch.zeros((B, keys.N + 1), dtype=torch.int32, device=dev)
+        cemu.blind_rotate_extract(keys, ops_t, pool, ia, ib, ext, form=form)
+    cemu.bootstrap_gates(keys, ops_t, pool, ia, ib, out, form=form)
+    torch.cuda.synchronize()
+    return (to_host_u32(ext) if want_ext else None), to_host_u32(out)
+
+
+def test_keys_match_oracle_toy(toy):
+    lk, ok = toy
+    ex = lk.export()
+    assert np.array_equal(ex["lwe_key"], ok.lwe_key)
+    assert np.array_equal(ex["tlwe_key"], ok.tlwe_key)
+    assert np.array_equal(ex["bk"], ok.bk)
+    assert np.array_equal(ex["ksk"], ok.ksk)
+
+
+def test_keys_match_oracle_std(std):
+    lk, ok = std
+    ex = lk.export()
+    assert np.array_equal(ex["lwe_key"], ok.lwe_key)
+    assert np.array_equal(ex["tlwe_key"], ok.tlwe_key)
+    assert np.array_equal(ex["bk"], ok.bk)
+    assert np.array_equal(ex["ksk"], ok.ksk)
+
+
+def test_encrypt_matches_oracle(toy):
+    lk, ok = toy
+    rng = np.random.default_rng(1)
+    bits = rng.integers(0, 2, 100).astype(np.uint8)
+    a = lk.encrypt(bits, seed=5, first_index=1000)
+    b = O.encrypt_bits(ok, bits, seed=5, first_index=1000)
+    assert np.array_equal(a, b)
+    assert np.array_equal(lk.decrypt(a), bits)
+
+
+def test_toy_eight_nand_bit_exact(toy, dev):
+    """Toy parameters, 8 independent NAND gates on uniform random bits."""
+    lk, ok = toy
+    say("[gpu] toy 8 NAND")
+    ops, a, b = W.gate_batch(8, seed=11, ops=(W.NAND,))
+    c1 = lk.encrypt(a, seed=21)
+    c2 = lk.encrypt(b, seed=21, first_index=8)
+    ext, out = run_gates(lk, ops, c1, c2, dev)
+    oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
+    assert np.array_equal(ext, oext)
+    assert np.array_equal(out, oout)
+    assert np.array_equal(lk.decrypt(out), (~(a & b)) & 1)
+
+
+def test_toy_all_gates_ragged_bit_exact(toy, dev):
+    """All ten gates x four input rows, plus a ragged tail (B = 43)."""
+    lk, ok = toy
+    say("[gpu] toy all gates ragged")
+    ops, a, b = W.all_gates_rows()
+    ops = np.concatenate([ops, ops[:3]])
+    a = np.concatenate([a, a[:3]])
+    b = np.concatenate([b, b[:3]])
+    c1 = lk.encrypt(a, seed=31)
+    c2 = lk.encrypt(b, seed=32)
+    ext, out = run_gates(lk, ops, c1, c2, dev)
+    oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
+    assert np.array_equal(ext, oext)
+    assert np.array_equal(out, oout)
+    truth = [lambda x, y: 1 - (x & y), lambda x, y: x & y, lambda x, y: x | y, lambda x, y: x ^ y,
+             lambda x, y: 1 - (x ^ y), lambda x, y: 1 - (x | y), lambda x, y: (1 - x) & y,
+             lambda x, y: x & (1 - y), lambda x, y: (1 - x) | y, lambda x, y: x | (1 - y)]
+    want = np.array([truth[o](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
+    assert np.array_equal(lk.decrypt(out), want)
+
+
+def test_std_batch_sampled_bit_exact(std, dev):
+    """Standard parameters, 4096-gate batch in the launch configuration of the
+    benchmark; every decryption exact, sampled gates bit-exact vs. oracle."""
+    lk, ok = std
+    B = 4096
+    say("[gpu] std 4096 batch")
+    ops, a, b = W.gate_batch(B, seed=41)
+    c1 = lk.encrypt(a, seed=W.ENC_SEED)
+    c2 = lk.encrypt(b, seed=W.ENC_SEED, first_index=B)
+    ext, out = run_gates(lk, ops, c1, c2, dev)
+    truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
+    want = np.array([truth[int(o)](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
+    assert np.array_equal(lk.decrypt(out), want)
+    assert np.array_equal(lk.decrypt_extracted(ext), want)
+    idx = W.sample_indices(B, 16, seed=42)
+    say(f"[gpu] oracle on {len(idx)} sampled gates")
+    oext, oout = O.bootstrap_batch(ok, ops[idx].astype(np.int32), c1[idx], c2[idx])
+    assert np.array_equal(ext[idx], oext)
+    assert np.array_equal(out[idx], oout)
+
+
+def test_key_switch_alone(std, dev):
+    lk, ok = std
+    rng = np.random.default_rng(7)
+    B = 37
+    ins = rng.integers(0, 1 << 32, (B, lk.N + 1), dtype=np.uint64).astype(np.uint32)
+    din = to_dev(ins, dev)
+    dout = torch.zeros((B, lk.n + 1), dtype=torch.int32, device=dev)
+    cemu.key_switch(lk, din, dout)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host_u32(dout), O.key_switch_batch(ok, ins))
+
+
+def test_gather_scatter_pool(toy, dev):
+    """Gates read arbitrary pool rows and write to arbitrary output rows."""
+    lk, ok = toy
+    rng = np.random.default_rng(8)
+    P = 20
+    bits = rng.integers(0, 2, P).astype(np.uint8)
+    pool = lk.encrypt(bits, seed=9)
+    B = 17
+    ia = rng.integers(0, P, B).astype(np.int32)
+    ib = rng.integers(0, P, B).astype(np.int32)
+    io = rng.permutation(40)[:B].astype(np.int32)
+    ops = rng.integers(0, 10, B).astype(np.uint8)
+    dpool = to_dev(pool, dev)
+    dout = torch.zeros((40, lk.n + 1), dtype=torch.int32, device=dev)
+    cemu.bootstrap_gates(lk, torch.from_numpy(ops).to(dev), dpool, torch.from_numpy(ia).to(dev),
+                         torch.from_numpy(ib).to(dev), dout, io=torch.from_numpy(io).to(dev))
+    torch.cuda.synchronize()
+    out = to_host_u32(dout)
+    _, oout = O.bootstrap_batch(ok, ops.astype(np.int32), pool[ia], pool[ib], want_extracted=False)
+    assert np.array_equal(out[io], oout)
+
+
+def test_empty_and_single(toy, dev):
+    lk, ok = toy
+    z = torch.zeros(0, dtype=torch.int32, device=dev)
+    cemu.bootstrap_gates(lk, torch.zeros(0, dtype=torch.uint8, device=dev), z, z, z,
+                         torch.zeros((0, lk.n + 1), dtype=torch.int32, device=dev))
+    ops = np.array([cemu.XOR], np.uint8)
+    c1 = lk.encrypt([1], seed=3)
+    c2 = lk.encrypt([1], seed=4)
+    ext, out = run_gates(lk, ops, c1, c2, dev)
+    oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
+    assert np.array_equal(out, oout)
+    assert lk.decrypt(out)[0] == 0
+
+
+def test_not_copy_constant(toy, dev):
+    lk, _ = toy
+    bits = np.array([0, 1, 1, 0], np.uint8)
+    c = lk.encrypt(bits, seed=13)
+    dpool = to_dev(c, dev)
+    idx = torch.arange(4, dtype=torch.int32, device=dev)
+    dnot = torch.zeros_like(dpool)
+    cemu.lwe_not(lk.n, dpool, idx, dnot, idx)
+    dcopy = torch.zeros_like(dpool)
+    cemu.lwe_copy(lk.n, dpool, idx, dcopy, idx.flip(0).contiguous())
+    dconst = torch.zeros_like(dpool)
+    cemu.lwe_constant(lk.n, torch.tensor([1, 0, 1, 1], dtype=torch.uint8, device=dev), dconst, idx)
+    torch.cuda.synchronize()
+    assert np.array_equal(lk.decrypt(to_host_u32(dnot)), 1 - bits)
+    assert np.array_equal(to_host_u32(dcopy), c[::-1])
+    assert np.array_equal(lk.decrypt(to_host_u32(dconst)), [1, 0, 1, 1])
+    assert np.array_equal(to_host_u32(dnot), (0 - c.astype(np.uint64)).astype(np.uint32))
+
+
+def test_errors_are_reported(toy, dev):
+    lk, _ = toy
+    z = torch.zeros(4, dtype=torch.int32, device=dev)
+    with pytest.raises(cemu.CemuError):
+        cemu._check(cemu.lib().cemu_bootstrap_gates(lk.ck, 7, None, None, None, None, None, None, 4, None))
+    with pytest.raises(cemu.CemuError):
+        cemu._check(cemu.lib().cemu_bootstrap_gates(lk.ck, 0, None, C.c_void_p(z.data_ptr()), None, None, None,
+                                                     None, 4, None))

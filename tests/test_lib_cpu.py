@@ -1,0 +1,61 @@
+"""Host-side checks of libcemu that need no GPU: the library loads, exports
+every entry point declared in include/cemu.h, fills parameter sets, and
+rejects bad arguments with error codes (no compute calls)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2101_03403_amd import cemu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "cemu.h")).read()
+    return sorted(set(re.findall(r"\b(cemu_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = cemu.lib()
+    names = declared_symbols()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(cemu.EXPORTED) == names
+
+
+def test_params_default():
+    p = cemu.params(cemu.STD)
+    assert (p.n, p.N, p.k, p.l, p.bgbit, p.t, p.basebit) == (630, 1024, 1, 3, 7, 8, 2)
+    assert p.sigma_lwe == 2.0 ** -15 and p.sigma_ks == 2.0 ** -15 and p.sigma_bk == 2.0 ** -25
+    t = cemu.params(cemu.TOY)
+    assert (t.n, t.N) == (256, 512)
+    with pytest.raises(cemu.CemuError) as e:
+        cemu.params(7)
+    assert e.value.code == -1
+
+
+@pytest.mark.parametrize("field,value,code", [("N", 2048, -6), ("l", 4, -6), ("bgbit", 8, -6), ("k", 2, -6),
+                                              ("basebit", 3, -6), ("t", 17, -1), ("n", 0, -1),
+                                              ("sigma_bk", -1.0, -1)])
+def test_keygen_rejects_unsupported_params_before_touching_the_gpu(field, value, code):
+    p = cemu.params(cemu.STD, **{field: value})
+    sk, ck = C.c_void_p(), C.c_void_p()
+    rc = cemu.lib().cemu_keygen(C.byref(p), 1, C.byref(sk), C.byref(ck))
+    assert rc == code
+    assert cemu.lib().cemu_last_error().decode()
+    assert not sk.value and not ck.value
+
+
+def test_null_and_range_errors():
+    L = cemu.lib()
+    assert L.cemu_params_default(None, 0) == -2
+    assert L.cemu_bootstrap_gates(None, 0, None, None, None, None, None, None, 4, None) == -2
+    assert L.cemu_key_switch(None, None, None, 1, None) == -2
+    assert L.cemu_lwe_not(630, None, None, None, None, -1, None) == -8
+    assert L.cemu_lwe_not(630, None, None, None, None, 0, None) == 0
+    assert L.cemu_encrypt(None, None, 0, 0, 0, None) == -2
+    assert L.cemu_export_keys(None, None, None, None, None, None) == 0
+    assert cemu.version().startswith("cemu")
