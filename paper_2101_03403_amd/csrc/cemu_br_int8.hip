@@ -22,9 +22,15 @@
 // generated fragment is reused for every (M-tile, K-tile) pair on that
 // diagonal: MT*KT / NDELTA = 512/92 (N = 1024) MFMAs per generated fragment.
 //
-// Waves: 4 per workgroup; wave w computes output component q = w/2 for rows
-// [h*N/2, (h+1)*N/2), h = w%2, and keeps the step's running sum in registers.
+// Per digit row p the workgroup first computes the digits of all 16 gates
+// into LDS (each digit once), then every wave loads its B operand from there.
+// Waves: WAVES per workgroup; the first half computes output component A,
+// the second half B, each wave a contiguous block of rows, and each keeps
+// the step's running sum in registers until the accumulators are updated.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
+#include <type_traits>
 
 #include "cemu_kernels.h"
 
@@ -32,195 +38,250 @@ namespace cemu {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
-constexpr int BR_G = 16;         // gates per workgroup = MFMA N dimension
-constexpr int BR_THREADS = 256;  // 4 waves
-constexpr int BR_ROWS = 6;       // (k+1) * l digit rows, k = 1, l = 3
-constexpr int LDS_PAD = 4;       // words of padding per accumulator row
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E). Used
+// wherever a register array is indexed, so that every index is a constant
+// and the arrays stay in registers.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
-template <int N>
+constexpr int BR_G = 16;    // gates per workgroup = MFMA N dimension
+constexpr int BR_ROWS = 6;  // (k+1) * l digit rows, k = 1, l = 3
+
+template <int N, int WAVES>
 struct BrShape {
-    static constexpr int HALF = N / 2;                          // rows per wave
-    static constexpr int MT = HALF / 16;                        // 16-row M-tiles per wave
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int PARTS = WAVES / 2;                     // waves per output component
+    static constexpr int RW = N / PARTS;                        // output rows per wave
+    static constexpr int MT = RW / 16;                          // 16-row M-tiles per wave
     static constexpr int KT = N / 64;                           // 64-wide K-tiles per digit row
-    static constexpr int ROW = N + LDS_PAD;                     // LDS words per (component, gate)
     static constexpr int RB = 2 * N;                            // bytes of one limb sequence R
     static constexpr int STAGE_BYTES = 2 * 4 * RB;              // R for one digit row: (q, limb)
     static constexpr int NDELTA = (MT - 1) + 4 * (KT - 1) + 1;  // distinct fragments per block
-    static constexpr int PRE = STAGE_BYTES / (BR_THREADS * 16); // uint4 per thread per stage
+    static constexpr int PRE = STAGE_BYTES / (THREADS * 16);    // u4 per thread per stage
+    static constexpr int CHUNKS = BR_G * N / 16;                // 16-digit chunks per digit row
+    static constexpr int CPT = CHUNKS / THREADS;                // chunks per thread
+    static_assert(PRE >= 1 && CPT >= 1 && MT >= 1, "shape");
 };
 
 // OFF = sum_{j=1..3} (Bg/2) 2^(32-7j) + 2^(32-21-1): adding it turns the
 // signed rounded digits into plain bit fields: d_j = ((x+OFF) >> (32-7j)) & 127) - 64.
 constexpr uint32_t kDigitOffset = 0x81020400u;
 
-// Digits of level j for the 16 gates, in MFMA B-operand layout: lane
-// (gate = lane&15, kgroup = lane>>4), K-tile b, byte e holds digit of
-// coefficient k = 64b + 16*kgroup + e of  X^a * P - P,  P = this lane's
-// accumulator component.
-template <int N>
-__device__ __forceinline__ void compute_bfrag(const uint32_t *__restrict__ row, uint32_t a, uint32_t sh, int g4,
-                                              v4i (&bf)[BrShape<N>::KT])
-{
-#pragma unroll
-    for (int b = 0; b < BrShape<N>::KT; ++b) {
-        const int k0 = 64 * b + 16 * g4;
-        const uint4 *up = reinterpret_cast<const uint4 *>(row + k0);
-        uint4 u4[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) u4[d] = up[d];
-        uint32_t packed[4];
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const uint32_t un[4] = {u4[d].x, u4[d].y, u4[d].z, u4[d].w};
-            uint32_t word = 0;
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                const uint32_t k = (uint32_t)(k0 + 4 * d + e4);
-                const uint32_t tt = (k - a) & (uint32_t)(2 * N - 1);
-                uint32_t v = row[tt & (uint32_t)(N - 1)];
-                v = (tt & (uint32_t)N) ? 0u - v : v;
-                const uint32_t y = v - un[e4] + kDigitOffset;
-                word |= ((y >> sh) & 127u) << (8 * e4);
-            }
-            // bytes x in [0,128) hold digit + 64; (x + 64) ^ 0x80 = x - 64 mod 256, no carries
-            packed[d] = (word + 0x40404040u) ^ 0x80808080u;
-        }
-        bf[b] = v4i{(int)packed[0], (int)packed[1], (int)packed[2], (int)packed[3]};
-    }
-}
+// Accumulator word k of gate g lives at g*N + (k ^ acc_swz(g)). The XOR keeps
+// 4-word groups contiguous and spreads the 16 gates over distinct LDS banks
+// for the column-wise (MFMA output) and row-wise (digit) access patterns.
+__device__ __forceinline__ uint32_t acc_swz(int g) { return (uint32_t)(((g & 3) << 4) | ((g >> 2) << 2)); }
 
-// acc[a] += T_tile(a, b) * D_tile(b) for all (a, b), one limb, fragments
-// generated once per diagonal delta = 4b - a.
-template <int N>
+// Digit chunk ch (digits of coefficients 16ch..16ch+15) of gate g lives at
+// byte g*N + 16*(ch ^ g): the 16 lanes that read one K-group hit 16 banks.
+__device__ __forceinline__ uint32_t dig_off(int N, int g, int ch) { return (uint32_t)(g * N + 16 * (ch ^ (g & 15))); }
+
+// acc[a] += T_tile(a, b) * D_tile(b) for all (a, b), one limb; a fragment is
+// generated once per diagonal delta = 4b - a and reused for every pair on it.
+template <int N, int WAVES>
 __device__ __forceinline__ void mfma_block(const uint32_t *__restrict__ pr, uint32_t shift,
-                                           v4i (&acc)[BrShape<N>::MT], const v4i (&bf)[BrShape<N>::KT])
+                                           v4i (&acc)[BrShape<N, WAVES>::MT], const v4i (&bf)[BrShape<N, WAVES>::KT])
 {
-    using S = BrShape<N>;
-    uint32_t w0 = pr[0];
-#pragma unroll
-    for (int di = 0; di < S::NDELTA; ++di) {
-        const uint32_t w1 = pr[4 * di + 1], w2 = pr[4 * di + 2], w3 = pr[4 * di + 3], w4 = pr[4 * di + 4];
+    using S = BrShape<N, WAVES>;
+    // Software pipeline: the dwords of fragment d+1 are requested before the
+    // MFMAs of fragment d are issued; sched_barrier keeps that order.
+    uint32_t w0 = pr[0], w1 = pr[1], w2 = pr[2], w3 = pr[3], w4 = pr[4];
+    static_for<0, S::NDELTA>([&](auto dI) {
+        constexpr int di = decltype(dI)::value;
         const v4i fr = v4i{(int)__builtin_amdgcn_alignbyte(w1, w0, shift), (int)__builtin_amdgcn_alignbyte(w2, w1, shift),
                            (int)__builtin_amdgcn_alignbyte(w3, w2, shift), (int)__builtin_amdgcn_alignbyte(w4, w3, shift)};
-#pragma unroll
-        for (int b = 0; b < S::KT; ++b) {
-            const int a = 4 * b - (di - (S::MT - 1));
-            if (a >= 0 && a < S::MT) acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[a], 0, 0, 0);
+        uint32_t n1 = 0, n2 = 0, n3 = 0, n4 = 0;
+        if constexpr (di + 1 < S::NDELTA) {
+            n1 = pr[4 * di + 5];
+            n2 = pr[4 * di + 6];
+            n3 = pr[4 * di + 7];
+            n4 = pr[4 * di + 8];
         }
+        static_for<0, S::KT>([&](auto bI) {
+            constexpr int b = decltype(bI)::value;
+            constexpr int a = 4 * b - (di - (S::MT - 1));
+            if constexpr (a >= 0 && a < S::MT) acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[a], 0, 0, 0);
+        });
         w0 = w4;
-    }
+        w1 = n1;
+        w2 = n2;
+        w3 = n3;
+        w4 = n4;
+        __builtin_amdgcn_sched_barrier(0);
+    });
 }
 
-template <int N>
-__global__ __launch_bounds__(BR_THREADS, 1) void br_int8_kernel(const uint8_t *__restrict__ bk8,
+template <int N, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *__restrict__ bk8,
                                                                 const uint16_t *__restrict__ bars, int32_t n,
                                                                 int64_t B, uint32_t *__restrict__ ext)
 {
-    using S = BrShape<N>;
-    __shared__ __attribute__((aligned(16))) uint32_t acc_s[2][BR_G][S::ROW];
+    using S = BrShape<N, WAVES>;
+    __shared__ __attribute__((aligned(16))) uint32_t acc_s[2][BR_G * N];
+    __shared__ __attribute__((aligned(16))) uint8_t dig[BR_G * N];
     __shared__ __attribute__((aligned(16))) uint32_t rst[S::STAGE_BYTES / 4];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int q = wave >> 1, h = wave & 1;
+    const int q = wave / S::PARTS, part = wave - q * S::PARTS;
     const int gl = lane & 15, g4 = lane >> 4;
     const int64_t g0 = (int64_t)blockIdx.x * BR_G;
     const int64_t barrow = (int64_t)n + 1;
     const bool live = g0 + gl < B;
     const uint16_t *mybars = bars + (g0 + gl) * barrow;
+    const uint32_t myswz = acc_swz(gl);
 
     // ACC = (0, X^{-bbar} v), v = (1/8) sum_j X^j.
-    for (int e = tid; e < BR_G * N; e += BR_THREADS) {
+    for (int e = tid; e < BR_G * N; e += S::THREADS) {
         const int g = e / N, m = e - (e / N) * N;
         const uint32_t bb = (g0 + g < B) ? (uint32_t)bars[(g0 + g) * barrow + n] : 0u;
         const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * N - 1);
-        acc_s[0][g][m] = 0u;
-        acc_s[1][g][m] = tt < (uint32_t)N ? 0x20000000u : 0xE0000000u;
+        const uint32_t ph = (uint32_t)(g * N) + ((uint32_t)m ^ acc_swz(g));
+        acc_s[0][ph] = 0u;
+        acc_s[1][ph] = tt < (uint32_t)N ? 0x20000000u : 0xE0000000u;
     }
 
-    // Lane's A-fragment source: s0 = N-1 - h*N/2 - r + 16*kgroup - 16*(MT-1) >= 0.
-    const int s0 = (N - 1) - h * S::HALF - gl + 16 * g4 - 16 * (S::MT - 1);
+    // Lane's A-fragment source: s0 = N-1 - part*RW - r + 16*kgroup - 16*(MT-1) >= 0.
+    const int s0 = (N - 1) - part * S::RW - gl + 16 * g4 - 16 * (S::MT - 1);
     const uint32_t frag_shift = (uint32_t)(s0 & 3);
     const int frag_dw = s0 >> 2;
 
-    uint4 pre[S::PRE];
-    auto load_stage = [&](int i, int p) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(bk8 + ((size_t)i * BR_ROWS + p) * S::STAGE_BYTES);
-#pragma unroll
-        for (int k = 0; k < S::PRE; ++k) pre[k] = src[tid + k * BR_THREADS];
-    };
-    load_stage(0, 0);
+    // Register-staged prefetch of the next digit row's key limbs.
+    u4 pre[S::PRE];
+    {
+        const u4 *src = reinterpret_cast<const u4 *>(bk8);
+        static_for<0, S::PRE>([&](auto kI) { pre[decltype(kI)::value] = src[tid + decltype(kI)::value * S::THREADS]; });
+    }
 
     uint32_t a_cur = live ? (uint32_t)mybars[0] : 0u;
     v4i total[S::MT];
 
     for (int i = 0; i < n; ++i) {
         const uint32_t a_next = (live && i + 1 < n) ? (uint32_t)mybars[i + 1] : 0u;
-#pragma unroll
-        for (int t = 0; t < S::MT; ++t) total[t] = v4i{0, 0, 0, 0};
+        static_for<0, S::MT>([&](auto tI) { total[decltype(tI)::value] = v4i{0, 0, 0, 0}; });
 
 #pragma unroll 1
         for (int p = 0; p < BR_ROWS; ++p) {
-            __syncthreads();  // previous users of rst are done; ACC updates visible
+            __syncthreads();  // previous digit row fully consumed; ACC updates visible
             {
-                uint4 *dst = reinterpret_cast<uint4 *>(rst);
-#pragma unroll
-                for (int k = 0; k < S::PRE; ++k) dst[tid + k * BR_THREADS] = pre[k];
+                u4 *dst = reinterpret_cast<u4 *>(rst);
+                static_for<0, S::PRE>([&](auto kI) { dst[tid + decltype(kI)::value * S::THREADS] = pre[decltype(kI)::value]; });
             }
             {
+                // next (step, row); past the last step reload row 0 (unused)
                 int ni = i, np = p + 1;
                 if (np == BR_ROWS) {
                     np = 0;
                     ++ni;
                 }
-                if (ni < n) load_stage(ni, np);
+                if (ni >= n) ni = 0;
+                const u4 *src = reinterpret_cast<const u4 *>(bk8 + ((size_t)ni * BR_ROWS + np) * S::STAGE_BYTES);
+                static_for<0, S::PRE>([&](auto kI) { pre[decltype(kI)::value] = src[tid + decltype(kI)::value * S::THREADS]; });
             }
-            __syncthreads();  // stage visible
+            // Digits of row p = (c, j) of X^a*ACC_c - ACC_c for all 16 gates:
+            // thread handles chunks f = tid + r*THREADS, gate f&15 (= gl).
+            {
+                const int c = p / 3, j = p - (p / 3) * 3;
+                const uint32_t sh = (uint32_t)(32 - 7 * (j + 1));
+                const uint32_t *row = &acc_s[c][gl * N];
+#pragma unroll 1
+                for (int r = 0; r < S::CPT; ++r) {
+                    const int ch = (tid + r * S::THREADS) >> 4;
+                    const int k0 = 16 * ch;
+                    uint32_t packed[4];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) {
+                        const u4 uw = *reinterpret_cast<const u4 *>(row + ((uint32_t)(k0 + 4 * d) ^ myswz));
+                        const uint32_t un[4] = {uw.x, uw.y, uw.z, uw.w};
+                        uint32_t word = 0;
+#pragma unroll
+                        for (int e4 = 0; e4 < 4; ++e4) {
+                            const uint32_t k = (uint32_t)(k0 + 4 * d + e4);
+                            const uint32_t tt = (k - a_cur) & (uint32_t)(2 * N - 1);
+                            uint32_t v = row[(tt & (uint32_t)(N - 1)) ^ myswz];
+                            v = (tt & (uint32_t)N) ? 0u - v : v;
+                            const uint32_t y = v - un[e4] + kDigitOffset;
+                            word |= ((y >> sh) & 127u) << (8 * e4);
+                        }
+                        // bytes x in [0,128) hold digit + 64; (x + 64) ^ 0x80 = x - 64 mod 256, no carries
+                        packed[d] = (word + 0x40404040u) ^ 0x80808080u;
+                    }
+                    *reinterpret_cast<u4 *>(dig + dig_off(N, gl, ch)) = u4{packed[0], packed[1], packed[2], packed[3]};
+                }
+            }
+            __syncthreads();  // digits and key stage visible
 
-            const int c = p / 3, j = p - (p / 3) * 3;
             v4i bf[S::KT];
-            compute_bfrag<N>(&acc_s[c][gl][0], a_cur, (uint32_t)(32 - 7 * (j + 1)), g4, bf);
+            static_for<0, S::KT>([&](auto bI) {
+                constexpr int b = decltype(bI)::value;
+                const u4 d4 = *reinterpret_cast<const u4 *>(dig + dig_off(N, gl, 4 * b + g4));
+                bf[b] = v4i{(int)d4.x, (int)d4.y, (int)d4.z, (int)d4.w};
+            });
 
             v4i acc[S::MT];
-#pragma unroll
-            for (int t = 0; t < S::MT; ++t) acc[t] = v4i{0, 0, 0, 0};
+            static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] = v4i{0, 0, 0, 0}; });
 #pragma unroll 1
             for (int kappa = 3; kappa >= 0; --kappa) {
-                if (kappa != 3) {
-#pragma unroll
-                    for (int t = 0; t < S::MT; ++t) acc[t] = acc[t] << 8;
-                }
+                if (kappa != 3) static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] <<= 8; });
                 const uint32_t *pr = rst + (q * 4 + kappa) * (S::RB / 4) + frag_dw;
-                mfma_block<N>(pr, frag_shift, acc, bf);
+                mfma_block<N, WAVES>(pr, frag_shift, acc, bf);
             }
-#pragma unroll
-            for (int t = 0; t < S::MT; ++t) total[t] += acc[t];
+            static_for<0, S::MT>([&](auto tI) { total[decltype(tI)::value] += acc[decltype(tI)::value]; });
         }
         __syncthreads();  // every wave has finished reading ACC for this step
-#pragma unroll
-        for (int t = 0; t < S::MT; ++t) {
-            uint4 *ptr = reinterpret_cast<uint4 *>(&acc_s[q][gl][h * S::HALF + 16 * t + 4 * g4]);
-            uint4 v = *ptr;
+        static_for<0, S::MT>([&](auto tI) {
+            constexpr int t = decltype(tI)::value;
+            const uint32_t m = (uint32_t)(part * S::RW + 16 * t + 4 * g4);
+            u4 *ptr = reinterpret_cast<u4 *>(&acc_s[q][gl * N + (m ^ myswz)]);
+            u4 v = *ptr;
             v.x += (uint32_t)total[t][0];
             v.y += (uint32_t)total[t][1];
             v.z += (uint32_t)total[t][2];
             v.w += (uint32_t)total[t][3];
             *ptr = v;
-        }
+        });
         a_cur = a_next;
     }
     __syncthreads();
 
     // Sample extraction: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0.
-    for (int e = tid; e < BR_G * (N + 1); e += BR_THREADS) {
+    for (int e = tid; e < BR_G * (N + 1); e += S::THREADS) {
         const int g = e / (N + 1), jj = e - (e / (N + 1)) * (N + 1);
         if (g0 + g >= B) continue;
+        const uint32_t base = (uint32_t)(g * N), sw = acc_swz(g);
         uint32_t v;
-        if (jj == 0) v = acc_s[0][g][0];
-        else if (jj == N) v = acc_s[1][g][0];
-        else v = 0u - acc_s[0][g][N - jj];
+        if (jj == 0) v = acc_s[0][base + (0u ^ sw)];
+        else if (jj == N) v = acc_s[1][base + (0u ^ sw)];
+        else v = 0u - acc_s[0][base + ((uint32_t)(N - jj) ^ sw)];
         ext[(g0 + g) * (N + 1) + jj] = v;
     }
+}
+
+// Waves per workgroup: 4 (one per SIMD, half the rows of one component each)
+// or 8 (two per SIMD, a quarter each). CEMU_BR_INT8_WAVES overrides.
+int br_int8_waves(int, int64_t)
+{
+    static const int env = [] {
+        const char *e = std::getenv("CEMU_BR_INT8_WAVES");
+        return e ? std::atoi(e) : 0;
+    }();
+    return env == 8 ? 8 : 4;
+}
+
+template <int N, int WAVES>
+int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
+{
+    const int64_t blocks = (B + BR_G - 1) / BR_G;
+    hipLaunchKernelGGL((br_int8_kernel<N, WAVES>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, ck->d_bk8, bars,
+                       ck->p.n, B, ext);
+    return CEMU_OK;
 }
 
 }  // namespace
@@ -229,14 +290,12 @@ int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, ui
 {
     const int64_t blocks = (B + BR_G - 1) / BR_G;
     if (blocks > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
-    if (ck->p.N == 1024)
-        hipLaunchKernelGGL(br_int8_kernel<1024>, dim3((unsigned)blocks), dim3(BR_THREADS), 0, s, ck->d_bk8, bars,
-                           ck->p.n, B, ext);
-    else if (ck->p.N == 512)
-        hipLaunchKernelGGL(br_int8_kernel<512>, dim3((unsigned)blocks), dim3(BR_THREADS), 0, s, ck->d_bk8, bars,
-                           ck->p.n, B, ext);
-    else
-        return fail(CEMU_ERR_UNSUPPORTED, "N must be 512 or 1024");
+    const int waves = br_int8_waves(ck->p.N, B);
+    int rc;
+    if (ck->p.N == 1024) rc = waves == 8 ? launch_shape<1024, 8>(ck, bars, B, ext, s) : launch_shape<1024, 4>(ck, bars, B, ext, s);
+    else if (ck->p.N == 512) rc = waves == 8 ? launch_shape<512, 8>(ck, bars, B, ext, s) : launch_shape<512, 4>(ck, bars, B, ext, s);
+    else return fail(CEMU_ERR_UNSUPPORTED, "N must be 512 or 1024");
+    if (rc) return rc;
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("br_int8_kernel launch: ") + hipGetErrorString(e));
     return CEMU_OK;
