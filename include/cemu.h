@@ -188,6 +188,18 @@ int cemu_export_keys(const cemu_secret_key *sk, const cemu_cloud_key *ck, int32_
 void cemu_free_secret_key(cemu_secret_key *sk);
 void cemu_free_cloud_key(cemu_cloud_key *ck);
 
+/* Kernel timing with HIP events. While enabled, every kernel the library
+ * launches for this cloud key is bracketed by a pair of hipEvents recorded on
+ * the same stream. cemu_profile_read waits for the recorded events, returns
+ * the summed durations in milliseconds and launch counts per kernel kind, and
+ * clears the record. Kinds: 0 = lincomb + modulus switch, 1 = blind rotation
+ * (int8), 2 = blind rotation (FFT64), 3 = key switch.
+ * ms, launches: host arrays of CEMU_PROFILE_KINDS entries (either may be NULL).
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_HIP. */
+enum { CEMU_PROFILE_KINDS = 4 };
+int cemu_profile_enable(cemu_cloud_key *ck, int enable);
+int cemu_profile_read(cemu_cloud_key *ck, double *ms, int64_t *launches);
+
 /* Description of the calling thread's last error ("" if none). */
 const char *cemu_last_error(void);
 

@@ -31,6 +31,9 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     int32_t n;        /* LWE dimension of gate ciphertexts                */
@@ -478,4 +481,14 @@ void or_gauss_array(uint64_t seed, int64_t count, double sigma, int64_t *out)
         or_block(seed, (uint32_t)e, (uint32_t)(e >> 32), 0, OR_DOM_ENC_NOISE, w);
         out[e] = or_gauss_from_block(w, sigma);
     }
+}
+
+/* Threads OpenMP will use for the batch routines. */
+int32_t or_num_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

@@ -101,6 +101,7 @@ def lib():
         L.or_modswitch_array.argtypes = [u32p, C.c_int64, C.c_int32, i32p]
         L.or_decompose_array.argtypes = [u32p, C.c_int64, C.c_int32, C.c_int32, i32p]
         L.or_gauss_array.argtypes = [C.c_uint64, C.c_int64, C.c_double, i64p]
+        L.or_num_threads.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -158,6 +159,10 @@ def gauss_array(seed: int, count: int, sigma: float) -> np.ndarray:
     out = np.zeros(count, np.int64)
     lib().or_gauss_array(seed, count, sigma, out)
     return out
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
 
 
 # ---------------------------------------------------------------- keys

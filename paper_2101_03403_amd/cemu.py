@@ -51,7 +51,9 @@ EXPORTED = [
     "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates",
     "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
+    "cemu_profile_enable", "cemu_profile_read",
 ]
+PROFILE_KINDS = ["lincomb_modswitch", "blind_rotate_int8", "blind_rotate_fft64", "key_switch"]
 
 _lib = None
 
@@ -85,6 +87,8 @@ def lib() -> C.CDLL:
     L.cemu_free_secret_key.restype = None
     L.cemu_free_cloud_key.argtypes = [vp]
     L.cemu_free_cloud_key.restype = None
+    L.cemu_profile_enable.argtypes = [vp, C.c_int]
+    L.cemu_profile_read.argtypes = [vp, vp, vp]
     L.cemu_last_error.restype = C.c_char_p
     L.cemu_version.restype = C.c_char_p
     for name in EXPORTED:
@@ -193,6 +197,19 @@ class Keys:
         _check(lib().cemu_export_keys(self.sk, self.ck, _np_ptr(lwe), _np_ptr(tlwe),
                                       _np_ptr(bka) if bk else None, _np_ptr(ksa) if ksk else None))
         return {"lwe_key": lwe, "tlwe_key": tlwe, "bk": bka, "ksk": ksa}
+
+
+def profile_enable(keys: Keys, enable: bool = True):
+    """Bracket every library kernel launch with hipEvents (see include/cemu.h)."""
+    _check(lib().cemu_profile_enable(keys.ck, int(enable)))
+
+
+def profile_read(keys: Keys) -> dict:
+    """{kind: (total_ms, launches)} since the last read; waits for the events."""
+    ms = np.zeros(len(PROFILE_KINDS), np.float64)
+    cnt = np.zeros(len(PROFILE_KINDS), np.int64)
+    _check(lib().cemu_profile_read(keys.ck, _np_ptr(ms), _np_ptr(cnt)))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROFILE_KINDS)}
 
 
 def keygen(p=STD, seed: int = 0) -> Keys:

@@ -264,15 +264,16 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
     }
 }
 
-// Waves per workgroup: 4 (one per SIMD, half the rows of one component each)
-// or 8 (two per SIMD, a quarter each). CEMU_BR_INT8_WAVES overrides.
+// Waves per workgroup: 8 (two per SIMD, a quarter of the rows of one
+// component each; the faster choice on MI355X) or 4 (one per SIMD, half the
+// rows each). CEMU_BR_INT8_WAVES=4 selects the latter.
 int br_int8_waves(int, int64_t)
 {
     static const int env = [] {
         const char *e = std::getenv("CEMU_BR_INT8_WAVES");
         return e ? std::atoi(e) : 0;
     }();
-    return env == 8 ? 8 : 4;
+    return env == 4 ? 4 : 8;
 }
 
 template <int N, int WAVES>

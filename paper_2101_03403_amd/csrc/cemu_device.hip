@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -171,6 +172,17 @@ __global__ void lwe_constant_kernel(int32_t n, const uint8_t *__restrict__ bits,
 
 inline bool misaligned(const void *p) { return ((uintptr_t)p & 3u) != 0; }
 
+// CEMU_KS_VALU=1 selects the VALU key-switching kernel (for comparison).
+bool ks_valu_forced()
+{
+    static const bool f = [] {
+        const char *e = std::getenv("CEMU_KS_VALU");
+        return e && e[0] == '1';
+    }();
+    return f;
+}
+
+
 int ensure_workspace(cemu_cloud_key *ck, int64_t B, bool need_ext)
 {
     const int32_t n = ck->p.n, N = ck->p.N;
@@ -207,9 +219,11 @@ int launch_lincomb(const cemu_cloud_key *ck, const uint8_t *ops, const uint32_t 
     const int64_t total = B * (n + 1);
     const int threads = 256;
     const int64_t blocks = (total + threads - 1) / threads;
+    void *ev = prof_begin(ck, s);
     hipLaunchKernelGGL(lincomb_modswitch_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, ops, pool, ia, ib, n,
                        log2_of(2 * ck->p.N), B, ck->d_bars);
     CEMU_HIP(hipGetLastError());
+    prof_end(ck, 0, s, ev);
     return CEMU_OK;
 }
 
@@ -218,6 +232,13 @@ int launch_key_switch(const cemu_cloud_key *ck, const uint32_t *ext, const int32
 {
     const int32_t n = ck->p.n, N = ck->p.N, t = ck->p.t;
     if (n + 1 > KS_COLS * KS_THREADS) return fail(CEMU_ERR_UNSUPPORTED, "key switch supports n <= 767");
+    void *ev = prof_begin(ck, s);
+    if (ck->d_ksk_mfma && ks_mfma_supported(ck->p) && !ks_valu_forced()) {
+        const int rc = launch_ks_mfma(ck, ext, io, out, B, s);
+        if (rc == CEMU_OK) prof_end(ck, 3, s, ev);
+        else if (ev) (void)hipEventDestroy((hipEvent_t)ev);
+        return rc;
+    }
     const int64_t blocks = (B + KS_G - 1) / KS_G;
     if (N == 1024)
         hipLaunchKernelGGL(key_switch_kernel<1024>, dim3((unsigned)blocks), dim3(KS_THREADS), 0, s, ext, ck->d_ksk, n,
@@ -226,6 +247,7 @@ int launch_key_switch(const cemu_cloud_key *ck, const uint32_t *ext, const int32
         hipLaunchKernelGGL(key_switch_kernel<512>, dim3((unsigned)blocks), dim3(KS_THREADS), 0, s, ext, ck->d_ksk, n,
                            t, B, io, out);
     CEMU_HIP(hipGetLastError());
+    prof_end(ck, 3, s, ev);
     return CEMU_OK;
 }
 
@@ -243,14 +265,43 @@ int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uin
 {
     int rc = launch_lincomb(ck, ops, pool, ia, ib, B, s);
     if (rc) return rc;
-    if (form == CEMU_FORM_INT8) return launch_br_int8(ck, ck->d_bars, B, ext_out, s);
-    if (form == CEMU_FORM_FFT64) return launch_br_fft(ck, ck->d_bars, B, ext_out, s);
-    return fail(CEMU_ERR_PARAM, "unknown product form");
+    void *ev = prof_begin(ck, s);
+    if (form == CEMU_FORM_INT8) rc = launch_br_int8(ck, ck->d_bars, B, ext_out, s);
+    else if (form == CEMU_FORM_FFT64) rc = launch_br_fft(ck, ck->d_bars, B, ext_out, s);
+    else rc = fail(CEMU_ERR_PARAM, "unknown product form");
+    if (rc == CEMU_OK) prof_end(ck, form == CEMU_FORM_INT8 ? 1 : 2, s, ev);
+    else if (ev) (void)hipEventDestroy((hipEvent_t)ev);
+    return rc;
 }
 
 }  // namespace
 
-int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const std::vector<uint32_t> &ksk)
+void *prof_begin(const cemu_cloud_key *ck, void *stream)
+{
+    if (!ck->profiling) return nullptr;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventRecord(e, (hipStream_t)stream) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return nullptr;
+    }
+    return (void *)e;
+}
+
+void prof_end(const cemu_cloud_key *ck, int kind, void *stream, void *start)
+{
+    if (!start) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, (hipStream_t)stream) != hipSuccess) {
+        if (e) (void)hipEventDestroy(e);
+        (void)hipEventDestroy((hipEvent_t)start);
+        return;
+    }
+    ck->prof.push_back({kind, start, (void *)e});
+}
+
+int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const std::vector<uint32_t> &ksk,
+                     const std::vector<uint8_t> &ksk_mfma)
 {
     CEMU_HIP(hipGetDevice(&ck->device));
     if (hipMalloc(&ck->d_bk8, bk8.size()) != hipSuccess) return fail(CEMU_ERR_OOM, "device allocation (BK) failed");
@@ -258,11 +309,17 @@ int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const 
         release_cloud_key(ck);
         return fail(CEMU_ERR_OOM, "device allocation (KSK) failed");
     }
+    if (!ksk_mfma.empty() && hipMalloc(&ck->d_ksk_mfma, ksk_mfma.size()) != hipSuccess) {
+        release_cloud_key(ck);
+        return fail(CEMU_ERR_OOM, "device allocation (KSK, MFMA layout) failed");
+    }
     hipError_t e1 = hipMemcpy(ck->d_bk8, bk8.data(), bk8.size(), hipMemcpyHostToDevice);
     hipError_t e2 = hipMemcpy(ck->d_ksk, ksk.data(), ksk.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    if (e1 != hipSuccess || e2 != hipSuccess) {
+    hipError_t e3 = ksk_mfma.empty() ? hipSuccess
+                                     : hipMemcpy(ck->d_ksk_mfma, ksk_mfma.data(), ksk_mfma.size(), hipMemcpyHostToDevice);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         release_cloud_key(ck);
-        return fail(CEMU_ERR_HIP, hip_msg("hipMemcpy (key upload)", e1 != hipSuccess ? e1 : e2));
+        return fail(CEMU_ERR_HIP, hip_msg("hipMemcpy (key upload)", e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
     }
     return CEMU_OK;
 }
@@ -287,11 +344,13 @@ void release_cloud_key(cemu_cloud_key *ck)
 {
     if (ck->d_bk8) (void)hipFree(ck->d_bk8);
     if (ck->d_ksk) (void)hipFree(ck->d_ksk);
+    if (ck->d_ksk_mfma) (void)hipFree(ck->d_ksk_mfma);
     if (ck->d_bkfft) (void)hipFree(ck->d_bkfft);
     if (ck->d_bars) (void)hipFree(ck->d_bars);
     if (ck->d_ext) (void)hipFree(ck->d_ext);
     ck->d_bk8 = nullptr;
     ck->d_ksk = nullptr;
+    ck->d_ksk_mfma = nullptr;
     ck->d_bkfft = nullptr;
     ck->d_bars = nullptr;
     ck->d_ext = nullptr;
@@ -356,9 +415,47 @@ int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *ou
     if (B == 0) return CEMU_OK;
     if (!in_N || !out_n) return fail(CEMU_ERR_NULL, "NULL device buffer");
     if (misaligned(in_N) || misaligned(out_n)) return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    std::lock_guard<std::mutex> lock(const_cast<cemu_cloud_key *>(ck)->mu);
     int rc = check_device(ck);
     if (rc) return rc;
     return launch_key_switch(ck, in_N, nullptr, out_n, B, (hipStream_t)hip_stream);
+}
+
+int cemu_profile_enable(cemu_cloud_key *ck, int enable)
+{
+    clear_error();
+    if (!ck) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    std::lock_guard<std::mutex> lock(ck->mu);
+    ck->profiling = enable != 0;
+    return CEMU_OK;
+}
+
+int cemu_profile_read(cemu_cloud_key *ck, double *ms, int64_t *launches)
+{
+    clear_error();
+    if (!ck) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    std::lock_guard<std::mutex> lock(ck->mu);
+    double sum[CEMU_PROFILE_KINDS] = {0, 0, 0, 0};
+    int64_t cnt[CEMU_PROFILE_KINDS] = {0, 0, 0, 0};
+    int rc = CEMU_OK;
+    for (auto &r : ck->prof) {
+        float t = 0.f;
+        hipError_t e = hipEventSynchronize((hipEvent_t)r.stop);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, (hipEvent_t)r.start, (hipEvent_t)r.stop);
+        if (e != hipSuccess && rc == CEMU_OK) rc = fail(CEMU_ERR_HIP, hip_msg("profile event", e));
+        if (r.kind >= 0 && r.kind < CEMU_PROFILE_KINDS) {
+            sum[r.kind] += t;
+            cnt[r.kind] += 1;
+        }
+        (void)hipEventDestroy((hipEvent_t)r.start);
+        (void)hipEventDestroy((hipEvent_t)r.stop);
+    }
+    ck->prof.clear();
+    for (int k = 0; k < CEMU_PROFILE_KINDS; ++k) {
+        if (ms) ms[k] = sum[k];
+        if (launches) launches[k] = cnt[k];
+    }
+    return rc;
 }
 
 static int launch_rowwise(int which, int32_t n, const uint32_t *in, const int32_t *src, const uint8_t *bits,

@@ -294,13 +294,27 @@ int cemu_keygen(const cemu_params *p, uint64_t seed, cemu_secret_key **sk_out, c
         }
     });
 
+    std::vector<uint8_t> ksk_mfma;
+    if (ks_mfma_supported(*p)) {
+        try {
+            ksk_mfma.resize(ks_mfma_bytes(*p));
+        } catch (...) {
+            delete sk;
+            return fail(CEMU_ERR_OOM, "host allocation failed");
+        }
+        const int ntiles = ks_mfma_ntiles(*p);
+        parallel_for((int64_t)4 * ntiles, [&](int64_t task) {
+            ks_mfma_arrange(*p, ksk.data(), ksk_mfma.data(), (int)(task / ntiles), (int)(task % ntiles));
+        });
+    }
+
     cemu_cloud_key *ck = new (std::nothrow) cemu_cloud_key;
     if (!ck) {
         delete sk;
         return fail(CEMU_ERR_OOM, "host allocation failed");
     }
     ck->p = *p;
-    rc = upload_cloud_key(ck, bk8, ksk);
+    rc = upload_cloud_key(ck, bk8, ksk, ksk_mfma);
     if (rc) {
         delete ck;
         delete sk;

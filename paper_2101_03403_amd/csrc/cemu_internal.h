@@ -27,6 +27,9 @@ struct cemu_cloud_key {
     uint8_t *d_bk8 = nullptr;
     // Key-switching key, canonical layout [N][t][2^basebit][n+1] words.
     uint32_t *d_ksk = nullptr;
+    // The same key as int8 limbs in MFMA B-operand order (see cemu_ks.hip),
+    // present when the parameters allow the MFMA key switch (t = 8).
+    uint8_t *d_ksk_mfma = nullptr;
     // Bootstrapping key in the FFT form (built on first use): for step i and
     // row r, component q, the twisted spectrum of the centred key polynomial,
     // [n][2l][2][N/2] complex doubles stored as (re, im).
@@ -37,6 +40,14 @@ struct cemu_cloud_key {
     uint32_t *d_ext = nullptr;   // [cap][N+1] extracted samples
     int64_t ext_cap = 0;
     std::mutex mu;
+    // Kernel timing (cemu_profile_enable): (kind, start, stop) event triples.
+    mutable bool profiling = false;
+    struct ProfileRec {
+        int kind;
+        void *start;
+        void *stop;
+    };
+    mutable std::vector<ProfileRec> prof;
 };
 
 namespace cemu {
@@ -48,8 +59,20 @@ void clear_error();
 // Parameter validation shared by host and device parts.
 int check_params(const cemu_params *p);
 
+// Kernel timing around one launch (cemu_device.hip). prof_begin returns an
+// opaque start event or nullptr when profiling is off.
+void *prof_begin(const cemu_cloud_key *ck, void *stream);
+void prof_end(const cemu_cloud_key *ck, int kind, void *stream, void *start);
+
 // Device-side helpers (cemu_device.hip).
-int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const std::vector<uint32_t> &ksk);
+int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const std::vector<uint32_t> &ksk,
+                     const std::vector<uint8_t> &ksk_mfma);
+
+// Key-switching key in MFMA fragment order (cemu_ks.hip).
+bool ks_mfma_supported(const cemu_params &p);
+size_t ks_mfma_bytes(const cemu_params &p);
+int ks_mfma_ntiles(const cemu_params &p);
+void ks_mfma_arrange(const cemu_params &p, const uint32_t *ksk, uint8_t *wf, int kappa, int ntile);
 int download_bk8(const cemu_cloud_key *ck, std::vector<uint8_t> &bk8);
 int download_ksk(const cemu_cloud_key *ck, std::vector<uint32_t> &ksk);
 void release_cloud_key(cemu_cloud_key *ck);

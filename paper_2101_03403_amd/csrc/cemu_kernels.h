@@ -13,4 +13,9 @@ namespace cemu {
 int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
 int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
 
+// Key switching of B extracted samples as an int8 MFMA contraction; output
+// row io[g] (or g) of out. Requires ks_mfma_supported(ck->p).
+int launch_ks_mfma(const cemu_cloud_key *ck, const uint32_t *ext, const int32_t *io, uint32_t *out, int64_t B,
+                   hipStream_t s);
+
 }  // namespace cemu
