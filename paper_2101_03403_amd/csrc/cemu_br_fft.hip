@@ -1,0 +1,395 @@
+// Blind rotation with FP64 negacyclic-FFT products (gfx950).
+//
+// Negacyclic product in R[X]/(X^N+1), N = 1024, through a length-N/2 complex
+// FFT: since X^N + 1 = (X^{N/2} - i)(X^{N/2} + i) and the polynomials are
+// real, P is determined by P mod (X^{N/2} - i) = sum_{j<N/2} (P_j + i P_{j+N/2}) X^j.
+// Substituting X = w Y with w = exp(i pi / N) (so w^{N/2} = i) turns that
+// ring into C[Y]/(Y^{N/2} - 1), where products are cyclic convolutions:
+//   z_j = (P_j + i P_{j+N/2}) w^j  ->  FFT_{N/2}  ->  pointwise products
+//   ->  inverse FFT / (N/2)  ->  times w^{-j}  ->  (R_j, R_{j+N/2}) = (Re, Im).
+// The key polynomials are taken as centred int32 values and their spectra
+// are precomputed once per key; digits are small integers. Sums reach about
+// 2^50 in magnitude, so the final rounding to integers can be off by a few
+// units in the last place of the torus: this form is approximate, unlike the
+// int8 form, and its deviation is measured against the oracle.
+//
+// FFT of 512 points per wave: lane l holds x[l + 64 m], m = 0..7. Three
+// radix-8 passes (512 = 8^3, decimation in frequency) with two LDS
+// transposes between them; the spectrum ends up with lane 8 k0 + k1 holding
+// X[k0 + 8 k1 + 64 k2] in slot k2, and the inverse runs the passes backwards
+// from that order, so no bit reversal is ever done. Key spectra are stored in
+// the same (slot, lane) order.
+//
+// One wave per gate, FG = 4 gates per workgroup: each wave keeps its
+// accumulator (2 x N u32) and its FFT transpose scratch in LDS; the key
+// spectra of one digit row (16 KiB) are staged in LDS once per workgroup,
+// prefetched through registers one row ahead.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "cemu_kernels.h"
+
+namespace cemu {
+namespace {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+constexpr int FN = 1024;          // ring degree handled by this kernel
+constexpr int FH = FN / 2;        // complex FFT length
+constexpr int SCR = 8 * 72;       // transpose scratch entries per wave (8 blocks of 64 + pad 8)
+constexpr uint32_t kDigitOffset = 0x81020400u;   // see cemu_br_int8.hip
+
+__device__ __forceinline__ d2 cmul(d2 a, d2 b) { return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ d2 cconj(d2 a) { return d2{a.x, -a.y}; }
+
+__device__ __forceinline__ d2 cexp_unit(double theta)
+{
+    double s, c;
+    sincos(theta, &s, &c);
+    return d2{c, s};
+}
+
+// In-register DFT of length 8 over x[0..7]; INV selects the +i sign.
+template <bool INV>
+__device__ __forceinline__ void dft8(d2 (&x)[8])
+{
+    const double r = 0.70710678118654752440;
+    d2 a0 = x[0] + x[4], a4 = x[0] - x[4];
+    d2 a1 = x[1] + x[5], a5 = x[1] - x[5];
+    d2 a2 = x[2] + x[6], a6 = x[2] - x[6];
+    d2 a3 = x[3] + x[7], a7 = x[3] - x[7];
+    if constexpr (!INV) {
+        a5 = d2{(a5.x + a5.y) * r, (a5.y - a5.x) * r};    // * (1 - i)/sqrt2
+        a6 = d2{a6.y, -a6.x};                              // * -i
+        a7 = d2{(a7.y - a7.x) * r, -(a7.x + a7.y) * r};   // * (-1 - i)/sqrt2
+    } else {
+        a5 = d2{(a5.x - a5.y) * r, (a5.x + a5.y) * r};    // * (1 + i)/sqrt2
+        a6 = d2{-a6.y, a6.x};                              // * i
+        a7 = d2{-(a7.x + a7.y) * r, (a7.x - a7.y) * r};   // * (-1 + i)/sqrt2
+    }
+    const d2 b0 = a0 + a2, b2 = a0 - a2, b1 = a1 + a3;
+    const d2 b4 = a4 + a6, b6 = a4 - a6, b5 = a5 + a7;
+    d2 b3 = a1 - a3, b7 = a5 - a7;
+    if constexpr (!INV) {
+        b3 = d2{b3.y, -b3.x};
+        b7 = d2{b7.y, -b7.x};
+    } else {
+        b3 = d2{-b3.y, b3.x};
+        b7 = d2{-b7.y, b7.x};
+    }
+    x[0] = b0 + b1;
+    x[4] = b0 - b1;
+    x[2] = b2 + b3;
+    x[6] = b2 - b3;
+    x[1] = b4 + b5;
+    x[5] = b4 - b5;
+    x[3] = b6 + b7;
+    x[7] = b6 - b7;
+}
+
+// x[s] *= b^s for s = 1..7.
+__device__ __forceinline__ void twiddle_pow(d2 (&x)[8], d2 b)
+{
+    d2 w = b;
+#pragma unroll
+    for (int s = 1; s < 8; ++s) {
+        x[s] = cmul(x[s], w);
+        if (s < 7) w = cmul(w, b);
+    }
+}
+
+// x[s] *= c * b^s for s = 0..7.
+__device__ __forceinline__ void twiddle_pow(d2 (&x)[8], d2 c, d2 b)
+{
+    d2 w = c;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        x[s] = cmul(x[s], w);
+        if (s < 7) w = cmul(w, b);
+    }
+}
+
+// Slot/lane transposes through the wave's scratch, hi = lane>>3, lo = lane&7.
+// Both maps are involutions:
+//   xpose_lo: out(hi, lo; s) = in(hi, s; lo)   (exchange lo with the slot)
+//   xpose_hi: out(hi, lo; s) = in(s, lo; hi)   (exchange hi with the slot)
+// Entry positions are a per-lane base plus a per-slot constant, and every
+// 16-lane group of an access hits 16 distinct 4-bank groups (72 = 8 mod 16
+// separates the two hi values of a group; 9 lo mod 16 is injective on 0..7).
+// The scratch is private to the wave and LDS operations of one wave execute
+// in order, so a wavefront-scope fence (compiler ordering only) suffices.
+__device__ __forceinline__ void wave_lds_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ __forceinline__ void xpose_lo(d2 (&x)[8], d2 *scr, int lane)
+{
+    const int hi = lane >> 3, lo = lane & 7;
+    d2 *w = scr + 72 * hi + lo;          // entry (hi, a = s, b = lo): 72 hi + 9 s + lo
+    d2 *r = scr + 72 * hi + 9 * lo;      // entry (hi, a = lo, b = s): 72 hi + 9 lo + s
+#pragma unroll
+    for (int s = 0; s < 8; ++s) w[9 * s] = x[s];
+    wave_lds_fence();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) x[s] = r[s];
+    wave_lds_fence();
+}
+
+__device__ __forceinline__ void xpose_hi(d2 (&x)[8], d2 *scr, int lane)
+{
+    const int hi = lane >> 3, lo = lane & 7;
+    d2 *w = scr + lane;                  // entry (a = s, b = hi, lo): 72 s + 8 hi + lo
+    d2 *r = scr + 72 * hi + lo;          // entry (a = hi, b = s, lo): 72 hi + 8 s + lo
+#pragma unroll
+    for (int s = 0; s < 8; ++s) w[72 * s] = x[s];
+    wave_lds_fence();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) x[s] = r[8 * s];
+    wave_lds_fence();
+}
+
+// Twiddle bases of one lane (W = exp(-2 pi i / 512)).
+struct Tw {
+    d2 f1;    // W^lane                       (forward pass 1, powers over slot)
+    d2 f2;    // W^(8 (lane & 7))             (forward pass 2; conj for inverse pass 1)
+    d2 i2c;   // W^-((lane & 7) (lane >> 3))  (inverse pass 2, constant factor)
+    d2 i2b;   // W^-(8 (lane >> 3))           (inverse pass 2, power base)
+};
+
+__device__ __forceinline__ Tw make_tw(int lane)
+{
+    const double two_pi_over = -2.0 * 3.14159265358979323846 / FH;
+    Tw t;
+    t.f1 = cexp_unit(two_pi_over * lane);
+    t.f2 = cexp_unit(two_pi_over * (8 * (lane & 7)));
+    t.i2c = cexp_unit(-two_pi_over * ((lane & 7) * (lane >> 3)));
+    t.i2b = cexp_unit(-two_pi_over * (8 * (lane >> 3)));
+    return t;
+}
+
+// Forward FFT_512: in x[m] = z[lane + 64 m]; out slot k2 of lane 8 k0 + k1 = Z[k0 + 8 k1 + 64 k2].
+__device__ __forceinline__ void fft_fwd(d2 (&x)[8], d2 *scr, int lane, const Tw &t)
+{
+    dft8<false>(x);                 // lane (j1, j0): over j2 -> k0
+    twiddle_pow(x, t.f1);           // W^((8 j1 + j0) k0)
+    xpose_hi(x, scr, lane);         // lane (k0, j0), slot j1
+    __builtin_amdgcn_sched_barrier(0);
+    dft8<false>(x);                 // over j1 -> k1
+    twiddle_pow(x, t.f2);           // W^(8 j0 k1)
+    xpose_lo(x, scr, lane);         // lane (k0, k1), slot j0
+    __builtin_amdgcn_sched_barrier(0);
+    dft8<false>(x);                 // over j0 -> k2
+}
+
+// Inverse (unscaled): the data movement of fft_fwd run backwards.
+__device__ __forceinline__ void fft_inv(d2 (&x)[8], d2 *scr, int lane, const Tw &t)
+{
+    dft8<true>(x);                  // lane (k0, k1): over k2 -> j0
+    twiddle_pow(x, cconj(t.f2));    // W^-(8 k1 j0)
+    xpose_lo(x, scr, lane);         // lane (k0, j0), slot k1
+    __builtin_amdgcn_sched_barrier(0);
+    dft8<true>(x);                  // over k1 -> j1
+    twiddle_pow(x, t.i2c, t.i2b);   // W^-((8 j1 + j0) k0)
+    xpose_hi(x, scr, lane);         // lane (j1, j0), slot k0
+    __builtin_amdgcn_sched_barrier(0);
+    dft8<true>(x);                  // over k0 -> j2
+}
+
+// exp(i pi m / 16), m = 0..7: the twist w^(64 m) of slot m.
+__device__ __forceinline__ d2 twist_slot(int m)
+{
+    const double c[8] = {1.0, 0.98078528040323044913, 0.92387953251128675613, 0.83146961230254523708,
+                         0.70710678118654752440, 0.55557023301960222474, 0.38268343236508977173,
+                         0.19509032201612826785};
+    return d2{c[m], c[(8 - m) & 7] * (m ? 1.0 : 0.0)};
+}
+
+// Key spectrum preparation: one wave per (step i, digit row r, component q).
+// Reads the int8-limb key (R[u] = limb(E[2N-1-u]), BK[m] at u = N-1-m),
+// centres each Torus32 coefficient, folds, twists and transforms.
+__global__ __launch_bounds__(64) void bk_fft_prepare_kernel(const uint8_t *__restrict__ bk8, d2 *__restrict__ spec)
+{
+    __shared__ d2 scr[SCR];
+    const int lane = threadIdx.x;
+    const int64_t poly = blockIdx.x;            // (i*6 + r)*2 + q
+    const uint8_t *base = bk8 + poly * 4 * (2 * FN);
+    const Tw t = make_tw(lane);
+    const d2 wl = cexp_unit(3.14159265358979323846 / FN * lane);
+    d2 x[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        double v[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int j = lane + 64 * m + h * FH;
+            const int u = FN - 1 - j;
+            uint32_t val = 0;
+#pragma unroll
+            for (int k = 3; k >= 0; --k) val = (val << 8) + (uint32_t)(int32_t)(int8_t)base[k * (2 * FN) + u];
+            v[h] = (double)(int32_t)val;
+        }
+        x[m] = cmul(d2{v[0], v[1]}, cmul(wl, twist_slot(m)));
+    }
+    fft_fwd(x, scr, lane, t);
+    d2 *dst = spec + poly * FH;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) dst[s * 64 + lane] = x[s];
+}
+
+constexpr int FG = 4;                      // gates (waves) per workgroup: one wave per SIMD, 512 registers each
+constexpr int F_THREADS = 64 * FG;
+constexpr int STAGE_D2 = 2 * FH;           // key spectra of one digit row: (q, slot, lane)
+constexpr int F_PRE = STAGE_D2 / F_THREADS; // d2 per thread per stage
+
+__global__ __launch_bounds__(F_THREADS, 1) void br_fft_kernel(const d2 *__restrict__ spec,
+                                                              const uint16_t *__restrict__ bars, int32_t n, int64_t B,
+                                                              uint32_t *__restrict__ ext)
+{
+    __shared__ uint32_t acc_all[FG][2][FN];
+    __shared__ d2 scr_all[FG][SCR];
+    __shared__ d2 kst[STAGE_D2];               // key spectra of the current digit row
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t g = (int64_t)blockIdx.x * FG + wave;
+    const bool live = g < B;
+    uint32_t(&acc)[2][FN] = acc_all[wave];
+    d2 *scr = scr_all[wave];
+    const uint16_t *bar = bars + (live ? g : 0) * (int64_t)(n + 1);
+    const Tw t = make_tw(lane);
+    const d2 wl = cexp_unit(3.14159265358979323846 / FN * lane);     // w^lane; twist of slot m = wl * twist_slot(m)
+
+    // ACC = (0, X^{-bbar} v)
+    const uint32_t bb = live ? bar[n] : 0u;
+    for (int m = lane; m < FN; m += 64) {
+        const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * FN - 1);
+        acc[0][m] = 0u;
+        acc[1][m] = tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+    }
+
+    d2 pre[F_PRE];
+    static_for<0, F_PRE>([&](auto kI) { pre[decltype(kI)::value] = spec[tid + decltype(kI)::value * F_THREADS]; });
+
+    uint32_t a_next = live ? bar[0] : 0u;
+    for (int i = 0; i < n; ++i) {
+        const uint32_t a = a_next;
+        if (live && i + 1 < n) a_next = bar[i + 1];
+        d2 outA[8], outB[8];
+        static_for<0, 8>([&](auto sI) {
+            outA[decltype(sI)::value] = d2{0.0, 0.0};
+            outB[decltype(sI)::value] = d2{0.0, 0.0};
+        });
+#pragma unroll 1
+        for (int c = 0; c < 2; ++c) {
+            // D = X^a ACC_c - ACC_c at this lane's 16 coefficients (+ digit offset)
+            uint32_t dlo[8], dhi[8];
+            static_for<0, 8>([&](auto mI) {
+                constexpr int m = decltype(mI)::value;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const uint32_t j = (uint32_t)(lane + 64 * m + h * FH);
+                    const uint32_t tt = (j - a) & (uint32_t)(2 * FN - 1);
+                    uint32_t v = acc[c][tt & (uint32_t)(FN - 1)];
+                    v = (tt & (uint32_t)FN) ? 0u - v : v;
+                    const uint32_t d = v - acc[c][j] + kDigitOffset;
+                    if (h == 0) dlo[m] = d; else dhi[m] = d;
+                }
+            });
+#pragma unroll 1
+            for (int jj = 0; jj < 3; ++jj) {
+                const int p = 3 * c + jj;
+                __syncthreads();   // every wave is done with the previous key stage
+                static_for<0, F_PRE>([&](auto kI) { kst[tid + decltype(kI)::value * F_THREADS] = pre[decltype(kI)::value]; });
+                {
+                    int ni = i, np = p + 1;
+                    if (np == 6) {
+                        np = 0;
+                        ++ni;
+                    }
+                    if (ni >= n) ni = 0;   // past the last step: reload step 0 (unused)
+                    const d2 *src = spec + ((int64_t)ni * 6 + np) * STAGE_D2;
+                    static_for<0, F_PRE>([&](auto kI) { pre[decltype(kI)::value] = src[tid + decltype(kI)::value * F_THREADS]; });
+                }
+                __syncthreads();   // stage visible
+
+                const uint32_t sh = (uint32_t)(32 - 7 * (jj + 1));
+                d2 x[8];
+                static_for<0, 8>([&](auto mI) {
+                    constexpr int m = decltype(mI)::value;
+                    const double lo = (double)((int32_t)((dlo[m] >> sh) & 127u) - 64);
+                    const double hi = (double)((int32_t)((dhi[m] >> sh) & 127u) - 64);
+                    x[m] = cmul(d2{lo, hi}, cmul(wl, twist_slot(m)));
+                });
+                __builtin_amdgcn_sched_barrier(0);
+                fft_fwd(x, scr, lane, t);
+                __builtin_amdgcn_sched_barrier(0);
+                static_for<0, 8>([&](auto sI) {
+                    constexpr int sl = decltype(sI)::value;
+                    outA[sl] += cmul(x[sl], kst[sl * 64 + lane]);
+                    outB[sl] += cmul(x[sl], kst[FH + sl * 64 + lane]);
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // inverse transforms, untwist, round, accumulate (this wave's ACC only)
+        wave_lds_fence();
+        auto finish = [&](d2 (&x)[8], uint32_t *dst) {
+            fft_inv(x, scr, lane, t);
+            static_for<0, 8>([&](auto mI) {
+                constexpr int m = decltype(mI)::value;
+                const d2 y = cmul(x[m], cconj(cmul(wl, twist_slot(m)))) * (1.0 / FH);
+                const int j = lane + 64 * m;
+                dst[j] += (uint32_t)(int64_t)rint(y.x);
+                dst[j + FH] += (uint32_t)(int64_t)rint(y.y);
+            });
+        };
+        finish(outA, acc[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        finish(outB, acc[1]);
+        wave_lds_fence();
+    }
+
+    // sample extraction
+    if (live) {
+        uint32_t *e = ext + g * (FN + 1);
+        for (int j = lane; j <= FN; j += 64) {
+            uint32_t v;
+            if (j == 0) v = acc[0][0];
+            else if (j == FN) v = acc[1][0];
+            else v = 0u - acc[0][FN - j];
+            e[j] = v;
+        }
+    }
+}
+
+}  // namespace
+
+int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
+{
+    if (ck->p.N != FN) return fail(CEMU_ERR_UNSUPPORTED, "the FFT64 form is built for N = 1024");
+    const int n = ck->p.n;
+    if (!ck->d_bkfft) {
+        const size_t polys = (size_t)n * 6 * 2;
+        if (hipMalloc(&ck->d_bkfft, polys * FH * sizeof(d2)) != hipSuccess)
+            return fail(CEMU_ERR_OOM, "device allocation (FFT key) failed");
+        hipLaunchKernelGGL(bk_fft_prepare_kernel, dim3((unsigned)polys), dim3(64), 0, s, ck->d_bk8,
+                           reinterpret_cast<d2 *>(ck->d_bkfft));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("bk_fft_prepare launch: ") + hipGetErrorString(e));
+    }
+    if (B > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
+    const int64_t blocks = (B + FG - 1) / FG;
+    hipLaunchKernelGGL(br_fft_kernel, dim3((unsigned)blocks), dim3(F_THREADS), 0, s,
+                       reinterpret_cast<const d2 *>(ck->d_bkfft), bars, n, B, ext);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("br_fft_kernel launch: ") + hipGetErrorString(e));
+    return CEMU_OK;
+}
+
+}  // namespace cemu

@@ -302,9 +302,4 @@ int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, ui
     return CEMU_OK;
 }
 
-int launch_br_fft(cemu_cloud_key *, const uint16_t *, int64_t, uint32_t *, hipStream_t)
-{
-    return fail(CEMU_ERR_UNSUPPORTED, "the FFT64 form is not built yet");
-}
-
 }  // namespace cemu

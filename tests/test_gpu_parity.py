@@ -232,3 +232,32 @@ def test_errors_are_reported(toy, dev):
     with pytest.raises(cemu.CemuError):
         cemu._check(cemu.lib().cemu_bootstrap_gates(lk.ck, 0, None, C.c_void_p(z.data_ptr()), None, None, None,
                                                      None, 4, None))
+
+
+def to_i32(x):
+    x = np.asarray(x, dtype=np.uint32)
+    return x.astype(np.int64) - ((x >> 31).astype(np.int64) << 32)
+
+
+@pytest.mark.parametrize("B", [37, 512])
+def test_fft_form_decrypts_and_phase_error(std, dev, B):
+    """FP64-FFT form: every decryption exact; extracted samples compared with
+    the oracle on sampled gates (raw words and decrypted phase)."""
+    lk, ok = std
+    say(f"[gpu] fft64 form B={B}")
+    ops, a, b = W.gate_batch(B, seed=51 + B)
+    c1 = lk.encrypt(a, seed=61)
+    c2 = lk.encrypt(b, seed=61, first_index=B)
+    ext, out = run_gates(lk, ops, c1, c2, dev, form="fft64")
+    truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
+    want = np.array([truth[int(o)](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
+    assert np.array_equal(lk.decrypt(out), want)
+    assert np.array_equal(lk.decrypt_extracted(ext), want)
+    idx = W.sample_indices(B, 8, seed=B)
+    oext, _ = O.bootstrap_batch(ok, ops[idx].astype(np.int32), c1[idx], c2[idx], want_out=False)
+    perr = to_i32(lk.phase(ext[idx], extracted=True).astype(np.int64) - lk.phase(oext, extracted=True).astype(np.int64))
+    words_diff = int(np.sum(ext[idx] != oext))
+    werr = np.abs(to_i32(ext[idx].astype(np.int64) - oext.astype(np.int64))).max()
+    say(f"[gpu] fft64 vs oracle: max |phase error| = {np.abs(perr).max()}, differing words = {words_diff}"
+        f"/{oext.size}, max |word error| = {werr}")
+    assert np.abs(perr).max() < (1 << 20)
