@@ -4,11 +4,12 @@ One step = one pass of the whole hot path over one batch of 4096 independent
 bootstrapped gates (type uniform in NAND/AND/OR/XOR, uniform input bits,
 fresh encryptions) at the standard parameters n=630, N=1024, k=1, l=3,
 Bgbit=7, t=8, basebit=2: gate linear combination + modulus switch, blind
-rotation with the int8-MFMA products, sample extraction, key switching.
+rotation, sample extraction, key switching. Both product forms are timed:
+the FP64 negacyclic-FFT form (the reported value) and the exact int8-MFMA form.
 Inputs (keys, ciphertext pool, gate lists) are resident in HBM before the
 timed region. Prints one JSON line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--form int8|fft64]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fft64|int8] [--only]
                   [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -31,7 +32,32 @@ BATCH = 4096
 N_, n_, ROWS = 1024, 630, 6
 INT8_OPS_PER_GATE = n_ * ROWS * 2 * N_ * N_ * 4 * 2
 PEAK_INT8_OPS = 5.0e15          # MI355X dense int8 MFMA, ops/s
-PEAK_FP64_FLOPS = 78.6e12
+PEAK_FP64_FLOPS = 78.6e12        # MI355X FP64 vector, flop/s
+# FP64-FFT form per gate: n steps x (8 FFTs of 512 points at 5 n log2 n + twist
+# 6 x 512, plus 12 x 512 complex multiply-adds at 8 flop).
+FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
+
+
+# HBM bytes per launch of the blind-rotation kernels at B = 4096, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, scales from a
+# plain 1 GiB copy); summary and commands in profiles/. Valid only while the
+# kernel source is the one profiled (sha256 prefix), else reported as null.
+TRAFFIC = {
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "c1c32a57930cbcc8",
+              "bytes": 970_992 * 1024 * 2 + 16_416 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "d6b46fb8e0bdd172",
+             "bytes": 245_924 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
+}
+
+
+def traffic_bytes(form, B):
+    import hashlib
+    t = TRAFFIC[form]
+    try:
+        h = hashlib.sha256(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return t["bytes"] if (h == t["sha256_16"] and B == t["batch"]) else None
 
 
 def parse():
@@ -39,10 +65,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="int8", choices=["int8", "fft64"])
+    ap.add_argument("--form", default="fft64", choices=["int8", "fft64"],
+                    help="form whose throughput is the reported value (the other is timed too)")
+    ap.add_argument("--only", action="store_true", help="time only --form")
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (3 times) and exit; "
+                         "used to scale HBM byte counters")
     return ap.parse_args()
 
 
@@ -65,6 +96,47 @@ def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample):
             "bit_exact_vs_gpu": f"{match}/{sample}"}
 
 
+def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
+    """Times `steps` whole-path steps of one product form; returns (seconds, kernel profile)."""
+    import torch
+    from paper_2101_03403_amd import cemu
+
+    def step():
+        cemu.bootstrap_gates(keys, ops_t, pool, ia, ib, out, form=form, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cemu.profile_read(keys)                       # drop anything recorded so far
+    cemu.profile_enable(keys, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cemu.profile_enable(keys, False)
+    return wall, cemu.profile_read(keys)
+
+
+def roofline(form, prof, B):
+    if form == "int8":
+        ms, cnt = prof["blind_rotate_int8"]
+        avg = ms / max(cnt, 1)
+        ach = INT8_OPS_PER_GATE * B / (avg * 1e-3)
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s",
+                "frac": ach / PEAK_INT8_OPS, "traffic": traffic_bytes("int8", B), "kernel": "br_int8_kernel<1024, 8>",
+                "avg_ms": avg, "algorithmic_per_launch": INT8_OPS_PER_GATE * B,
+                "algorithmic_per_gate": "n*2l*2*N^2*4 limbs*2 = 6.34e10 int8 ops"}
+    ms, cnt = prof["blind_rotate_fft64"]
+    avg = ms / max(cnt, 1)
+    ach = FFT_FLOP_PER_GATE * B / (avg * 1e-3)
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
+            "frac": ach / PEAK_FP64_FLOPS, "traffic": traffic_bytes("fft64", B), "kernel": "br_fft_kernel",
+            "avg_ms": avg, "algorithmic_per_launch": FFT_FLOP_PER_GATE * B,
+            "algorithmic_per_gate": "n*(8*(5*512*9 + 6*512) + 12*512*8) = 1.63e8 FP64 flop"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -76,6 +148,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+        return
     keys = cemu.keygen(cemu.STD, W.KEY_SEED)
     B = args.batch
     ops, a, b = W.gate_batch(B, seed=1)
@@ -85,63 +166,48 @@ def main():
     ops_t = torch.from_numpy(ops).to(dev)
     ia = torch.arange(B, dtype=torch.int32, device=dev)
     ib = ia + B
-    out = torch.zeros((B, keys.n + 1), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-
-    def step():
-        cemu.bootstrap_gates(keys, ops_t, pool, ia, ib, out, form=args.form, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    cemu.profile_read(keys)                       # drop anything recorded so far
-    cemu.profile_enable(keys, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    cemu.profile_enable(keys, False)
-    prof = cemu.profile_read(keys)
-    ms_per_step = wall * 1e3 / args.steps
-    value = B / (wall / args.steps)
-
-    gpu_out = out.cpu().numpy().view(np.uint32)
     truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
     want = np.array([truth[int(o)](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
-    dec_ok = int(np.sum(keys.decrypt(gpu_out) == want))
 
-    br_kind = "blind_rotate_int8" if args.form == "int8" else "blind_rotate_fft64"
-    br_ms, br_n = prof[br_kind]
-    br_avg_ms = br_ms / max(br_n, 1)
-    if args.form == "int8":
-        achieved = INT8_OPS_PER_GATE * B / (br_avg_ms * 1e-3)
-        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s",
-                "frac": achieved / PEAK_INT8_OPS, "traffic": None,
-                "kernel": "br_int8_kernel<1024,8>", "avg_ms": br_avg_ms,
-                "algorithmic_ops_per_launch": INT8_OPS_PER_GATE * B}
-    else:
-        flops = 1.63e8 * B
-        achieved = flops / (br_avg_ms * 1e-3)
-        roof = {"bound": "fp64", "achieved": achieved / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_FLOPS, "traffic": None, "avg_ms": br_avg_ms}
-    kernels = {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()}
+    forms = [args.form] + [f for f in ("fft64", "int8") if f != args.form and not args.only]
+    res = {}
+    outs = {}
+    for form in forms:
+        out = torch.zeros((B, keys.n + 1), dtype=torch.int32, device=dev)
+        wall, prof = run_form(keys, form, ops_t, pool, ia, ib, out, stream, args.steps, args.warmup)
+        host = out.cpu().numpy().view(np.uint32)
+        outs[form] = host
+        res[form] = {
+            "value": B / (wall / args.steps), "ms_per_step": wall * 1e3 / args.steps,
+            "roofline": roofline(form, prof, B),
+            "kernels": {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()},
+            "decrypt_exact": f"{int(np.sum(keys.decrypt(host) == want))}/{B}",
+        }
+    primary = res[args.form]
+    if len(outs) == 2:
+        same = int(np.sum(np.all(outs["fft64"] == outs["int8"], axis=1)))
+        primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(W.KEY_SEED, ops, c1, c2, gpu_out, min(args.cpu_sample, B))
+        cpu = cpu_baseline(W.KEY_SEED, ops, c1, c2, outs[args.form], min(args.cpu_sample, B))
 
     rec = {
-        "metric": METRIC, "value": value, "unit": "gates/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int8" if args.form == "int8" else "f64", "data": "synthetic",
+        "metric": METRIC, "value": primary["value"], "unit": "gates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": primary["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.form == "fft64" else "int8", "data": "synthetic",
         "config": {"workload": f"{B} independent bootstrapped gates (NAND/AND/OR/XOR uniform, random bits), "
-                               "TFHE n=630 N=1024 k=1 l=3 Bgbit=7 t=8 basebit=2",
+                               "TFHE n=630 N=1024 k=1 l=3 Bgbit=7 t=8 basebit=2, "
+                               + ("FP64 negacyclic-FFT products" if args.form == "fft64"
+                                  else "int8-limb MFMA products"),
                    "form": args.form, "batch": B, "parallelism": "single GPU"},
-        "roofline": roof, "cpu_baseline": cpu, "kernels": kernels,
-        "decrypt_exact": f"{dec_ok}/{B}",
+        "roofline": primary["roofline"], "cpu_baseline": cpu,
+        "kernels": primary["kernels"], "decrypt_exact": primary["decrypt_exact"],
+        "forms": {f: {k: v for k, v in r.items() if k != "kernels"} for f, r in res.items()},
     }
+    if "identical_outputs_fft64_vs_int8" in primary:
+        rec["identical_outputs_fft64_vs_int8"] = primary["identical_outputs_fft64_vs_int8"]
     print(json.dumps(rec), flush=True)
 
 
