@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
+    ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
+    ap.add_argument("--add-instances", type=int, default=256)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit; "
                          "used to scale HBM byte counters")
@@ -117,6 +119,53 @@ def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
     wall = time.perf_counter() - t0
     cemu.profile_enable(keys, False)
     return wall, cemu.profile_read(keys)
+
+
+def add32_latency(keys, dev, form, instances=256, reps=3):
+    """32-bit Kogge-Stone ADD (Sec. 5.2): `instances` concurrent ADDs with all
+    gates of a level in one launch, the 12 levels captured as one hipGraph.
+    Latency = first level launch to last level done; also one instance alone."""
+    import torch
+    from paper_2101_03403_amd import circuits as Cc, workloads as W
+
+    out = {}
+    for inst in (instances, 1):
+        rng = np.random.default_rng(404 + inst)
+        ops = rng.integers(0, 1 << 32, (inst, 2), dtype=np.uint64)
+        cs = [Cc.adder_instance(32) for _ in range(inst)]
+        prog = Cc.Program(cs).to_device(dev)
+        bits = []
+        for a, b in ops:
+            bits += Cc.int_to_bits(int(a), 32) + Cc.int_to_bits(int(b), 32)
+        pool = torch.zeros((prog.rows, keys.n + 1), dtype=torch.int32, device=dev)
+        enc = keys.encrypt(np.asarray(bits, np.uint8), seed=W.ENC_SEED + inst)
+        pool[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = \
+            torch.from_numpy(enc.view(np.int32)).to(dev)
+        prog.run(keys, pool, form=form)                 # sizes the workspaces
+        torch.cuda.synchronize()
+        g = prog.capture(keys, pool, form=form)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        host = pool.cpu().numpy().view(np.uint32)
+        ok = 0
+        for k, (a, b) in enumerate(ops):
+            rows = np.array(cs[k].outputs["sum"]) + prog.offsets[k]
+            ok += int(Cc.bits_to_int(keys.decrypt(host[rows])) == (int(a) + int(b)) % (1 << 32))
+        ms = float(np.median(times))
+        key = "batch" if inst == instances else "single"
+        out[key] = {"instances": inst, "latency_ms": ms, "amortized_ms_per_add": ms / inst,
+                    "gates": prog.num_gates(), "levels": prog.depth, "gates_per_s": prog.num_gates() / (ms * 1e-3),
+                    "decrypt_exact": f"{ok}/{inst}", "level_widths": prog.level_widths()}
+    out["form"] = form
+    out["timing"] = "hipGraph of the 12 level launches, median of 3 replays (hip events)"
+    return out
 
 
 def roofline(form, prof, B):
@@ -189,6 +238,11 @@ def main():
         same = int(np.sum(np.all(outs["fft64"] == outs["int8"], axis=1)))
         primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
 
+    if not args.no_add:
+        rec_add = add32_latency(keys, dev, args.form)
+    else:
+        rec_add = None
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(W.KEY_SEED, ops, c1, c2, outs[args.form], min(args.cpu_sample, B))
@@ -206,6 +260,8 @@ def main():
         "kernels": primary["kernels"], "decrypt_exact": primary["decrypt_exact"],
         "forms": {f: {k: v for k, v in r.items() if k != "kernels"} for f, r in res.items()},
     }
+    if rec_add is not None:
+        rec["add32"] = rec_add
     if "identical_outputs_fft64_vs_int8" in primary:
         rec["identical_outputs_fft64_vs_int8"] = primary["identical_outputs_fft64_vs_int8"]
     print(json.dumps(rec), flush=True)

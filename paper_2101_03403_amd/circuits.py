@@ -1,0 +1,393 @@
+"""Gate-level circuits of CryptoEmu's functional units and the level scheduler
+that runs them on the GPU.
+
+Circuits (built from bootstrapped binary gates plus the free NOT / CONSTANT):
+  * ``kogge_stone_add`` -- the parallel-prefix adder of Sec. 5.2: stage 1
+    computes (g_i, p_i) = (a_i AND b_i, a_i XOR b_i) (Fig. get_gp); stage 2
+    applies the operator (g_x, p_x) o (g_y, p_y) = (g_x + p_x g_y, p_x p_y) in
+    log2 W levels, each level at distance d = 1, 2, 4, ... and each o made of
+    AND -> OR on the carry and AND on the propagate (Fig. get_carry); stage 3
+    sums s_i = p_i XOR G_{i-1} with G_{-1} = carry-in. For W = 32 the levels
+    hold [64 | 62, 31 | 60, 30 | 56, 28 | 48, 24 | 32, 16 | 32] gates
+    (o counts 31, 30, 28, 24, 16 as in the text of Sec. 5.2), 483 in total,
+    depth 2 log2 W + 2 = 12.
+  * ``subtract`` -- a + NOT(b) + 1 (Sec. 5.3): unbootstrapped NOT of b, the
+    carry-in folded into bit 0 by one OR, and the sum bit 0 by one XOR with a
+    constant (the subtractor's two extra bootstrapped gates).
+  * ``less_than`` (borrow of a - b), ``equal`` (XNOR + AND tree),
+    ``bitwise`` (one gate per bit, Sec. 5.7) and ``array_multiply`` (AND
+    partial products accumulated with Kogge-Stone adders) -- the compare,
+    bitwise and multiply instructions of the mixed instruction stream.
+
+Execution: ``Program`` takes any number of circuit instances, assigns each
+bootstrapped gate to a level (one more than its latest bootstrapped input,
+i.e. the paper's stage order), and merges the gates of one level across all
+instances into a single batched launch (gather from / scatter to one device
+ciphertext pool). The launch sequence can be captured once as a hipGraph and
+replayed.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import cemu
+
+NAND, AND, OR, XOR, XNOR, NOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
+
+_PLAIN = {
+    NAND: lambda a, b: 1 - (a & b), AND: lambda a, b: a & b, OR: lambda a, b: a | b,
+    XOR: lambda a, b: a ^ b, XNOR: lambda a, b: 1 - (a ^ b), NOR: lambda a, b: 1 - (a | b),
+    ANDNY: lambda a, b: (1 - a) & b, ANDYN: lambda a, b: a & (1 - b),
+    ORNY: lambda a, b: (1 - a) | b, ORYN: lambda a, b: a | (1 - b),
+}
+
+
+@dataclass
+class Circuit:
+    """A DAG over wires. Kinds: 'in', 'gate' (bootstrapped), 'not', 'const'.
+
+    Every wire has a level: 0 for inputs and constants, the input's level for
+    NOT, and for a gate the larger of 1 + its inputs' levels and a requested
+    level (used to keep the paper's stage structure, where every o of one
+    prefix level runs in the same stage)."""
+    nodes: list = field(default_factory=list)      # (kind, op, a, b)
+    lv: list = field(default_factory=list)         # level of each wire
+    inputs: list = field(default_factory=list)     # wire ids fed from outside
+    outputs: dict = field(default_factory=dict)    # name -> list of wires
+
+    def _new(self, kind, op=-1, a=-1, b=-1, level=0) -> int:
+        self.nodes.append((kind, op, a, b))
+        self.lv.append(level)
+        return len(self.nodes) - 1
+
+    def input(self) -> int:
+        w = self._new("in")
+        self.inputs.append(w)
+        return w
+
+    def inputs_word(self, width: int) -> list:
+        return [self.input() for _ in range(width)]
+
+    def gate(self, op: int, a: int, b: int, level: int = 0) -> int:
+        return self._new("gate", op, a, b, max(1 + max(self.lv[a], self.lv[b]), level))
+
+    def NOT(self, a: int) -> int:
+        return self._new("not", -1, a, -1, self.lv[a])
+
+    def const(self, bit: int) -> int:
+        return self._new("const", int(bit))
+
+    # ---------------------------------------------------------- evaluation
+    def eval_plain(self, in_bits) -> np.ndarray:
+        """Evaluate on cleartext bits (for structure tests)."""
+        vals = np.zeros(len(self.nodes), np.int64)
+        it = iter(in_bits)
+        for w, (kind, op, a, b) in enumerate(self.nodes):
+            if kind == "in":
+                vals[w] = next(it)
+            elif kind == "gate":
+                vals[w] = _PLAIN[op](int(vals[a]), int(vals[b]))
+            elif kind == "not":
+                vals[w] = 1 - vals[a]
+            else:
+                vals[w] = op
+        return vals
+
+    def levels(self) -> np.ndarray:
+        return np.array(self.lv, dtype=np.int64)
+
+    def gate_counts_per_level(self) -> list:
+        gl = [self.lv[w] for w, n in enumerate(self.nodes) if n[0] == "gate"]
+        if not gl:
+            return []
+        gl = np.array(gl)
+        return [int(np.sum(gl == L)) for L in range(1, int(gl.max()) + 1)]
+
+    def depth(self) -> int:
+        return max([self.lv[w] for w, n in enumerate(self.nodes) if n[0] == "gate"], default=0)
+
+    def num_gates(self) -> int:
+        return sum(1 for n in self.nodes if n[0] == "gate")
+
+
+# ------------------------------------------------------------------ circuits
+def kogge_stone_add(c: Circuit, A: list, B: list, carry_in: int | None = None):
+    """Parallel-prefix adder (Sec. 5.2). A, B: wires, LSB first. carry_in:
+    None (0) or 1 (constant). Returns (sum wires, carry-out wire).
+
+    Stages relative to the inputs' level: 1 = (g, p); for prefix level k
+    (distance 2^(k-1)): 2k = the two ANDs of every o, 2k+1 = its OR; last =
+    the sum XORs."""
+    W = len(A)
+    base = max(c.lv[w] for w in list(A) + list(B))
+    g = [c.gate(AND, A[i], B[i], base + 1) for i in range(W)]
+    p = [c.gate(XOR, A[i], B[i], base + 1) for i in range(W)]
+    G = list(g)
+    P = list(p)
+    if carry_in == 1:
+        # carry out of bit 0 with carry-in 1: g_0 + p_0 * 1 (one extra OR)
+        G[0] = c.gate(OR, g[0], p[0], base + 2)
+    d, k = 1, 1
+    while d < W:
+        tmp = {i: c.gate(AND, P[i], G[i - d], base + 2 * k) for i in range(d, W)}
+        newP = {i: c.gate(AND, P[i], P[i - d], base + 2 * k) for i in range(d, W)}
+        newG = {i: c.gate(OR, G[i], tmp[i], base + 2 * k + 1) for i in range(d, W)}
+        for i in range(d, W):
+            G[i] = newG[i]
+            P[i] = newP[i]
+        d *= 2
+        k += 1
+    last = base + 2 * k
+    cin = c.const(1 if carry_in == 1 else 0)
+    s = [c.gate(XOR, p[0], cin, last)] + [c.gate(XOR, p[i], G[i - 1], last) for i in range(1, W)]
+    return s, G[W - 1]
+
+
+def subtract(c: Circuit, A: list, B: list):
+    """a - b = a + NOT(b) + 1 (Sec. 5.3). Returns (difference wires, carry-out
+    wire; carry-out 1 means no borrow, i.e. a >= b unsigned)."""
+    nb = [c.NOT(b) for b in B]
+    return kogge_stone_add(c, A, nb, carry_in=1)
+
+
+def less_than(c: Circuit, A: list, B: list) -> int:
+    """Unsigned a < b: the borrow of a - b, i.e. NOT(carry-out)."""
+    _, carry = subtract(c, A, B)
+    return c.NOT(carry)
+
+
+def equal(c: Circuit, A: list, B: list) -> int:
+    """a == b: XNOR per bit, then a balanced AND tree."""
+    layer = [c.gate(XNOR, a, b) for a, b in zip(A, B)]
+    while len(layer) > 1:
+        nxt = [c.gate(AND, layer[i], layer[i + 1]) for i in range(0, len(layer) - 1, 2)]
+        if len(layer) % 2:
+            nxt.append(layer[-1])
+        layer = nxt
+    return layer[0]
+
+
+def bitwise(c: Circuit, op: int, A: list, B: list) -> list:
+    """One bootstrapped gate per bit (Sec. 5.7)."""
+    return [c.gate(op, a, b) for a, b in zip(A, B)]
+
+
+def _full_add(c: Circuit, a: int, b: int, cin: int):
+    """Full adder of bootstrapped gates: s = a ^ b ^ cin, cout = ab + cin(a ^ b)."""
+    t = c.gate(XOR, a, b)
+    s = c.gate(XOR, t, cin)
+    cout = c.gate(OR, c.gate(AND, a, b), c.gate(AND, t, cin))
+    return s, cout
+
+
+def array_multiply(c: Circuit, A: list, B: list) -> list:
+    """Unsigned W x W -> 2W product as an array multiplier: the W^2 AND partial
+    products (one level), rows accumulated in carry-save form with full and
+    half adders, and a final Kogge-Stone adder for the sum and carry vectors.
+    Known-zero positions are skipped rather than computed."""
+    W = len(A)
+    ZERO = None
+    S = [ZERO] * (2 * W)     # sum vector (None = constant 0)
+    Cv = [ZERO] * (2 * W)    # carry vector, already aligned to its weight
+    for i in range(W):
+        row = [ZERO] * (2 * W)
+        for j in range(W):
+            row[i + j] = c.gate(AND, A[j], B[i])
+        newS, newC = [ZERO] * (2 * W), [ZERO] * (2 * W)
+        for k in range(2 * W):
+            ins = [w for w in (S[k], Cv[k], row[k]) if w is not None]
+            if len(ins) == 0:
+                continue
+            if len(ins) == 1:
+                newS[k] = ins[0]
+            elif len(ins) == 2:
+                newS[k] = c.gate(XOR, ins[0], ins[1])
+                if k + 1 < 2 * W:
+                    newC[k + 1] = c.gate(AND, ins[0], ins[1])
+            else:
+                sk, ck = _full_add(c, *ins)
+                newS[k] = sk
+                if k + 1 < 2 * W:
+                    newC[k + 1] = ck
+        S, Cv = newS, newC
+    zero = c.const(0)
+    Sw = [w if w is not None else zero for w in S]
+    Cw = [w if w is not None else zero for w in Cv]
+    out, _ = kogge_stone_add(c, Sw, Cw)
+    return out
+
+
+def adder_instance(width: int, carry_in_one: bool = False):
+    """A standalone W-bit ADD (or SUB if carry_in_one and inputs negated by the
+    caller) circuit: inputs a[0..W), b[0..W); output 'sum'."""
+    c = Circuit()
+    A = c.inputs_word(width)
+    B = c.inputs_word(width)
+    s, _ = kogge_stone_add(c, A, B)
+    c.outputs["sum"] = s
+    return c
+
+
+def sub_instance(width: int):
+    c = Circuit()
+    A = c.inputs_word(width)
+    B = c.inputs_word(width)
+    s, _ = subtract(c, A, B)
+    c.outputs["diff"] = s
+    return c
+
+
+def int_to_bits(v: int, width: int) -> list:
+    return [(int(v) >> i) & 1 for i in range(width)]
+
+
+def bits_to_int(bits) -> int:
+    return int(sum(int(b) << i for i, b in enumerate(bits)))
+
+
+# ------------------------------------------------------------------ scheduler
+@dataclass
+class Level:
+    ops: np.ndarray     # uint8 [G]
+    ia: np.ndarray      # int32 [G] pool rows
+    ib: np.ndarray
+    io: np.ndarray
+    nots: tuple         # (src rows, dst rows) executed before the level's gates
+
+
+class Program:
+    """Many circuit instances merged level by level into batched launches.
+
+    Pool layout: every wire of every instance gets one row of a device
+    ciphertext pool [rows][n+1]; instance k's wire w is row offset[k] + w.
+    """
+
+    def __init__(self, circuits: list):
+        self.circuits = circuits
+        self.offsets = np.cumsum([0] + [len(c.nodes) for c in circuits])
+        self.rows = int(self.offsets[-1])
+        per_level = {}
+        nots = {}
+        consts = ([], [])
+        for k, c in enumerate(circuits):
+            off = int(self.offsets[k])
+            for w, (kind, op, a, b) in enumerate(c.nodes):
+                L = c.lv[w]
+                if kind == "gate":
+                    per_level.setdefault(L, []).append((op, off + a, off + b, off + w))
+                elif kind == "not":
+                    nots.setdefault(L, []).append((off + a, off + w))
+                elif kind == "const":
+                    consts[0].append(op)
+                    consts[1].append(off + w)
+        depth = max(per_level) if per_level else 0
+        self.levels = []
+        for L in range(1, depth + 1):
+            arr = np.array(per_level.get(L, []), dtype=np.int64).reshape(-1, 4)
+            na = np.array(nots.get(L - 1, []), dtype=np.int64).reshape(-1, 2)
+            self.levels.append(Level(arr[:, 0].astype(np.uint8), arr[:, 1].astype(np.int32),
+                                     arr[:, 2].astype(np.int32), arr[:, 3].astype(np.int32),
+                                     (na[:, 0].astype(np.int32), na[:, 1].astype(np.int32))))
+        # NOTs of the last level's outputs run after the last launch
+        tail = np.array(nots.get(depth, []), dtype=np.int64).reshape(-1, 2)
+        self.tail_nots = (tail[:, 0].astype(np.int32), tail[:, 1].astype(np.int32))
+        self.consts = (np.array(consts[0], np.uint8), np.array(consts[1], np.int32))
+        self.input_rows = np.concatenate([np.array(c.inputs, np.int64) + int(self.offsets[k])
+                                          for k, c in enumerate(circuits)]).astype(np.int32)
+        self._dev = None
+        self._graph = None
+
+    @property
+    def depth(self) -> int:
+        return len(self.levels)
+
+    def level_widths(self) -> list:
+        return [int(L.ops.shape[0]) for L in self.levels]
+
+    def num_gates(self) -> int:
+        return int(sum(self.level_widths()))
+
+    # ------------------------------------------------------------ device side
+    def to_device(self, device):
+        import torch
+
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+        self._dev = {
+            "levels": [(t(L.ops), t(L.ia), t(L.ib), t(L.io), t(L.nots[0]), t(L.nots[1])) for L in self.levels],
+            "tail": (t(self.tail_nots[0]), t(self.tail_nots[1])),
+            "consts": (t(self.consts[0]), t(self.consts[1])),
+        }
+        return self
+
+    def run(self, keys, pool, form="fft64", stream=None, profile_levels=None):
+        """Enqueue the whole program on `stream`: constants, then per level the
+        NOTs it needs and one batched gate launch (gather/scatter in `pool`)."""
+        import torch
+        if self._dev is None:
+            self.to_device(pool.device)
+        d = self._dev
+        n = keys.n
+        if d["consts"][1].shape[0]:
+            cemu.lwe_constant(n, d["consts"][0], pool, d["consts"][1], stream=stream)
+        for li, (ops, ia, ib, io, ns, nd) in enumerate(d["levels"]):
+            if ns.shape[0]:
+                cemu.lwe_not(n, pool, ns, pool, nd, stream=stream)
+            ev = None
+            if profile_levels is not None:
+                ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                ev[0].record(stream)
+            cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=form, stream=stream)
+            if ev is not None:
+                ev[1].record(stream)
+                profile_levels.append(ev)
+        if d["tail"][0].shape[0]:
+            cemu.lwe_not(n, pool, d["tail"][0], pool, d["tail"][1], stream=stream)
+
+    def capture(self, keys, pool, form="fft64"):
+        """Capture the level sequence as one hipGraph (after an eager run has
+        sized the library's workspaces). Returns the torch graph object."""
+        import torch
+        stream = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(stream):
+            with torch.cuda.graph(g, stream=stream):
+                self.run(keys, pool, form=form, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        self._graph = g
+        return g
+
+
+def instruction_circuit(kind: str, width: int) -> Circuit:
+    """One instruction of the mixed stream as a circuit with inputs a, b
+    (width bits each, LSB first) and output 'out'."""
+    c = Circuit()
+    A = c.inputs_word(width)
+    B = c.inputs_word(width)
+    if kind == "ADD":
+        out, _ = kogge_stone_add(c, A, B)
+    elif kind == "SUB":
+        out, _ = subtract(c, A, B)
+    elif kind == "MUL":
+        out = array_multiply(c, A, B)
+    elif kind == "LT":
+        out = [less_than(c, A, B)]
+    elif kind == "EQ":
+        out = [equal(c, A, B)]
+    elif kind in ("AND", "OR", "XOR"):
+        out = bitwise(c, {"AND": AND, "OR": OR, "XOR": XOR}[kind], A, B)
+    else:
+        raise ValueError(f"unknown instruction {kind}")
+    c.outputs["out"] = out
+    return c
+
+
+def instruction_result(kind: str, width: int, a: int, b: int) -> int:
+    """Cleartext result the circuit must decrypt to."""
+    m = (1 << width) - 1
+    return {"ADD": (a + b) & m, "SUB": (a - b) & m, "MUL": a * b, "LT": int(a < b), "EQ": int(a == b),
+            "AND": a & b, "OR": a | b, "XOR": a ^ b}[kind]

@@ -45,3 +45,32 @@ def sample_indices(B: int, k: int, seed: int):
     rest = rng.choice(B, size=max(0, k - len(fixed)), replace=False)
     idx = sorted(set([i for i in fixed if 0 <= i < B]) | set(int(x) for x in rest))
     return np.array(idx[:max(k, len(fixed))], dtype=np.int64)
+
+
+# Mixed instruction stream: 40 % ADD/SUB, 20 % array MUL (8x8 or 16x16),
+# 20 % compare (LT/EQ), 20 % bitwise AND/OR/XOR; widths 8/16/32 uniform
+# (MUL 8 or 16), operands uniform at the width.
+MIX_KINDS = ("ADD", "SUB", "MUL", "LT", "EQ", "AND", "OR", "XOR")
+
+
+def instruction_mix(count: int, seed: int):
+    """[(kind, width, a, b)] for `count` independent instructions."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        u = rng.random()
+        if u < 0.4:
+            kind = "ADD" if rng.random() < 0.5 else "SUB"
+            width = int(rng.choice([8, 16, 32]))
+        elif u < 0.6:
+            kind = "MUL"
+            width = int(rng.choice([8, 16]))
+        elif u < 0.8:
+            kind = "LT" if rng.random() < 0.5 else "EQ"
+            width = int(rng.choice([8, 16, 32]))
+        else:
+            kind = str(rng.choice(["AND", "OR", "XOR"]))
+            width = int(rng.choice([8, 16, 32]))
+        a, b = (int(x) for x in rng.integers(0, 1 << width, 2, dtype=np.uint64))
+        out.append((kind, width, a, b))
+    return out

@@ -1,0 +1,120 @@
+"""Circuit structure and scheduling, on the CPU.
+
+Structure is pinned by the paper's own counts: the 32-bit Kogge-Stone adder
+has o counts 31, 30, 28, 24, 16 per prefix level and the 16-bit one 15, 14,
+12, 8 (Sec. 5.2, thread counts of Table 16BitAdderStages / 32BitAdderStages
+discussion), depth 2 log2 W + 2 (Sec. 7.1), and subtraction is a + NOT(b) + 1
+(Sec. 5.3). Function is pinned by cleartext evaluation against integer
+arithmetic, and by one small circuit evaluated gate by gate with the CPU
+oracle (toy parameters) and decrypted.
+"""
+import numpy as np
+import pytest
+
+from paper_2101_03403_amd import circuits as C
+from paper_2101_03403_amd import workloads as W
+
+
+def test_adder_levels_match_paper_32():
+    c = C.adder_instance(32)
+    assert c.gate_counts_per_level() == [64, 62, 31, 60, 30, 56, 28, 48, 24, 32, 16, 32]
+    assert c.num_gates() == 483
+    assert c.depth() == 2 * 5 + 2
+    # o counts per prefix level = ORs in the odd levels 3, 5, 7, 9, 11
+    ors = [c.gate_counts_per_level()[L] for L in (2, 4, 6, 8, 10)]
+    assert ors == [31, 30, 28, 24, 16]
+
+
+def test_adder_levels_match_paper_16():
+    c = C.adder_instance(16)
+    assert c.gate_counts_per_level() == [32, 30, 15, 28, 14, 24, 12, 16, 8, 16]
+    assert c.depth() == 2 * 4 + 2
+
+
+@pytest.mark.parametrize("width", [8, 16, 32])
+def test_add_sub_cleartext(width):
+    rng = np.random.default_rng(width)
+    add, sub = C.adder_instance(width), C.sub_instance(width)
+    assert sub.num_gates() == add.num_gates() + 1          # carry-in OR
+    vals = list(rng.integers(0, 1 << width, (200, 2), dtype=np.uint64)) + [(0, 0), ((1 << width) - 1, 1),
+                                                                             (0, (1 << width) - 1)]
+    for a, b in vals:
+        a, b = int(a), int(b)
+        bits = C.int_to_bits(a, width) + C.int_to_bits(b, width)
+        assert C.bits_to_int(add.eval_plain(bits)[add.outputs["sum"]]) == (a + b) % (1 << width)
+        assert C.bits_to_int(sub.eval_plain(bits)[sub.outputs["diff"]]) == (a - b) % (1 << width)
+
+
+@pytest.mark.parametrize("kind", W.MIX_KINDS)
+@pytest.mark.parametrize("width", [8, 16])
+def test_instruction_circuits_cleartext(kind, width):
+    rng = np.random.default_rng(hash((kind, width)) % 1000)
+    c = C.instruction_circuit(kind, width)
+    for _ in range(40):
+        a, b = (int(x) for x in rng.integers(0, 1 << width, 2, dtype=np.uint64))
+        if kind in ("LT", "EQ") and rng.random() < 0.3:
+            b = a
+        v = c.eval_plain(C.int_to_bits(a, width) + C.int_to_bits(b, width))
+        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, width, a, b)
+
+
+def test_program_merges_levels_across_instances():
+    cs = [C.adder_instance(32) for _ in range(3)] + [C.sub_instance(16)]
+    prog = C.Program(cs)
+    widths = prog.level_widths()
+    assert sum(widths) == 3 * 483 + 196
+    assert widths[0] == 3 * 64 + 32
+    assert prog.depth == 12
+    # every gate's inputs are produced at an earlier level (or are inputs/consts/NOTs)
+    produced = set(prog.input_rows.tolist()) | set(prog.consts[1].tolist())
+    for L in prog.levels:
+        produced |= set(L.nots[1].tolist())
+        assert set(L.ia.tolist()) <= produced and set(L.ib.tolist()) <= produced
+        produced |= set(L.io.tolist())
+
+
+def test_mixed_stream_recipe():
+    mix = W.instruction_mix(1000, seed=5)
+    kinds = [k for k, *_ in mix]
+    frac = lambda ks: sum(k in ks for k in kinds) / len(kinds)
+    assert abs(frac({"ADD", "SUB"}) - 0.4) < 0.05
+    assert abs(frac({"MUL"}) - 0.2) < 0.05
+    assert abs(frac({"LT", "EQ"}) - 0.2) < 0.05
+    assert all(w in (8, 16) for k, w, *_ in mix if k == "MUL")
+
+
+def _run_with_oracle(prog, okeys, in_bits, enc_seed=3):
+    """Execute a Program level by level with the CPU oracle (test only)."""
+    from oracle import oracle as O
+    p = okeys.params
+    pool = np.zeros((prog.rows, p.n + 1), np.uint32)
+    pool[prog.input_rows] = O.encrypt_bits(okeys, np.asarray(in_bits, np.uint8), seed=enc_seed)
+    for bit, row in zip(prog.consts[0], prog.consts[1]):
+        pool[row] = 0
+        pool[row, p.n] = 0x20000000 if bit else 0xE0000000
+    for L in prog.levels:
+        src, dst = L.nots
+        pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
+        _, out = O.bootstrap_batch(okeys, L.ops.astype(np.int32), pool[L.ia], pool[L.ib], want_extracted=False)
+        pool[L.io] = out
+    src, dst = prog.tail_nots
+    pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
+    return pool
+
+
+def test_small_circuits_under_fhe_with_oracle():
+    """8-bit ADD and SUB plus a 4-bit EQ and LT, evaluated homomorphically
+    gate by gate with the oracle (toy parameters), then decrypted."""
+    from oracle import oracle as O
+    okeys = O.keygen(O.TOY, 99)
+    cases = [("ADD", 8, 200, 100), ("SUB", 8, 17, 50), ("EQ", 4, 9, 9), ("LT", 4, 3, 12)]
+    cs = [C.instruction_circuit(k, w) for k, w, _, _ in cases]
+    prog = C.Program(cs)
+    bits = []
+    for k, w, a, b in cases:
+        bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
+    pool = _run_with_oracle(prog, okeys, bits)
+    for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
+        rows = np.array(c.outputs["out"]) + off
+        got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
+        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
