@@ -18,7 +18,7 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcemu.so")
+LIB_PATH = os.environ.get("CEMU_LIB") or os.path.join(HERE, "libcemu.so")
 
 STD, TOY = 0, 1
 FORM_INT8, FORM_FFT64 = 0, 1

@@ -20,7 +20,8 @@
 // from that order, so no bit reversal is ever done. Key spectra are stored in
 // the same (slot, lane) order.
 //
-// One wave per gate, FG = 4 gates per workgroup: each wave keeps its
+// One wave per gate, FG = 8 gates per workgroup (two waves per SIMD, which
+// measured faster than one wave per SIMD with twice the registers): each wave keeps its
 // accumulator (2 x N u32) and its FFT transpose scratch in LDS; the key
 // spectra of one digit row (16 KiB) are staged in LDS once per workgroup,
 // prefetched through registers one row ahead.
@@ -164,6 +165,17 @@ struct Tw {
     d2 i2b;   // W^-(8 (lane >> 3))           (inverse pass 2, power base)
 };
 
+// Hide a value's provenance from the optimiser so that products of it
+// (twiddle and twist powers) are recomputed where they are used instead of
+// being hoisted out of the step loop: hoisting them all would overflow the
+// 256 registers a wave has at two waves per SIMD.
+__device__ __forceinline__ void launder(d2 &v)
+{
+    double a = v.x, b = v.y;
+    asm volatile("" : "+v"(a), "+v"(b));
+    v = d2{a, b};
+}
+
 __device__ __forceinline__ Tw make_tw(int lane)
 {
     const double two_pi_over = -2.0 * 3.14159265358979323846 / FH;
@@ -244,7 +256,7 @@ __global__ __launch_bounds__(64) void bk_fft_prepare_kernel(const uint8_t *__res
     for (int s = 0; s < 8; ++s) dst[s * 64 + lane] = x[s];
 }
 
-constexpr int FG = 4;                      // gates (waves) per workgroup: one wave per SIMD, 512 registers each
+constexpr int FG = 8;                      // gates (waves) per workgroup: two waves per SIMD
 constexpr int F_THREADS = 64 * FG;
 constexpr int STAGE_D2 = 2 * FH;           // key spectra of one digit row: (q, slot, lane)
 constexpr int F_PRE = STAGE_D2 / F_THREADS; // d2 per thread per stage
@@ -262,8 +274,9 @@ __global__ __launch_bounds__(F_THREADS, 1) void br_fft_kernel(const d2 *__restri
     uint32_t(&acc)[2][FN] = acc_all[wave];
     d2 *scr = scr_all[wave];
     const uint16_t *bar = bars + (live ? g : 0) * (int64_t)(n + 1);
-    const Tw t = make_tw(lane);
-    const d2 wl = cexp_unit(3.14159265358979323846 / FN * lane);     // w^lane; twist of slot m = wl * twist_slot(m)
+    const Tw t0 = make_tw(lane);
+    const d2 wl0 = cexp_unit(3.14159265358979323846 / FN * lane);
+    Tw t = t0; d2 wl = wl0;
 
     // ACC = (0, X^{-bbar} v)
     const uint32_t bb = live ? bar[n] : 0u;
@@ -280,6 +293,7 @@ __global__ __launch_bounds__(F_THREADS, 1) void br_fft_kernel(const d2 *__restri
     for (int i = 0; i < n; ++i) {
         const uint32_t a = a_next;
         if (live && i + 1 < n) a_next = bar[i + 1];
+        launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b); launder(wl);
         d2 outA[8], outB[8];
         static_for<0, 8>([&](auto sI) {
             outA[decltype(sI)::value] = d2{0.0, 0.0};
