@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
     ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
     ap.add_argument("--add-instances", type=int, default=256)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed instruction stream")
+    ap.add_argument("--no-autotune", action="store_true", help="circuits use --form with default tiles")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit; "
                          "used to scale HBM byte counters")
@@ -121,7 +123,7 @@ def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
     return wall, cemu.profile_read(keys)
 
 
-def add32_latency(keys, dev, form, instances=256, reps=3):
+def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None):
     """32-bit Kogge-Stone ADD (Sec. 5.2): `instances` concurrent ADDs with all
     gates of a level in one launch, the 12 levels captured as one hipGraph.
     Latency = first level launch to last level done; also one instance alone."""
@@ -141,9 +143,9 @@ def add32_latency(keys, dev, form, instances=256, reps=3):
         enc = keys.encrypt(np.asarray(bits, np.uint8), seed=W.ENC_SEED + inst)
         pool[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = \
             torch.from_numpy(enc.view(np.int32)).to(dev)
-        prog.run(keys, pool, form=form)                 # sizes the workspaces
+        prog.run(keys, pool, form=form, tuner=tuner)    # sizes the workspaces, tunes each width
         torch.cuda.synchronize()
-        g = prog.capture(keys, pool, form=form)
+        g = prog.capture(keys, pool, form=form, tuner=tuner)
         times = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -163,9 +165,46 @@ def add32_latency(keys, dev, form, instances=256, reps=3):
         out[key] = {"instances": inst, "latency_ms": ms, "amortized_ms_per_add": ms / inst,
                     "gates": prog.num_gates(), "levels": prog.depth, "gates_per_s": prog.num_gates() / (ms * 1e-3),
                     "decrypt_exact": f"{ok}/{inst}", "level_widths": prog.level_widths()}
-    out["form"] = form
+    out["form"] = form if tuner is None else "autotuned per level width"
     out["timing"] = "hipGraph of the 12 level launches, median of 3 replays (hip events)"
     return out
+
+
+def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
+    """1024 independent instructions (40 % ADD/SUB, 20 % 8x8/16x16 array MUL,
+    20 % LT/EQ, 20 % AND/OR/XOR; widths 8/16/32), gates of each level merged
+    across instructions into one launch. Makespan of one warm run."""
+    import torch
+    from paper_2101_03403_amd import circuits as Cc, workloads as W
+
+    mix = W.instruction_mix(count, seed)
+    cs = [Cc.instruction_circuit(k, w) for k, w, _, _ in mix]
+    prog = Cc.Program(cs).to_device(dev)
+    bits = []
+    for k, w, a, b in mix:
+        bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
+    pool = torch.zeros((prog.rows, keys.n + 1), dtype=torch.int32, device=dev)
+    enc = keys.encrypt(np.asarray(bits, np.uint8), seed=W.ENC_SEED + 7)
+    pool[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = torch.from_numpy(enc.view(np.int32)).to(dev)
+    prog.run(keys, pool, form=form, tuner=tuner)   # warm-up (sizes workspaces, tunes widths)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    prog.run(keys, pool, form=form, tuner=tuner)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    host = pool.cpu().numpy().view(np.uint32)
+    ok = 0
+    for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
+        ok += int(Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"]) + off])) ==
+                  Cc.instruction_result(k, w, a, b))
+    widths = np.array(prog.level_widths())
+    hist = {f"<{lim}": int(np.sum(widths < lim)) for lim in (256, 1024, 4096, 16384)}
+    hist[">=16384"] = int(np.sum(widths >= 16384))
+    return {"instructions": count, "makespan_ms": ms, "gates": prog.num_gates(), "levels": prog.depth,
+            "gates_per_s": prog.num_gates() / (ms * 1e-3), "decrypt_exact": f"{ok}/{count}",
+            "level_width_histogram": hist, "form": form if tuner is None else "autotuned per level width"}
 
 
 def roofline(form, prof, B):
@@ -238,10 +277,12 @@ def main():
         same = int(np.sum(np.all(outs["fft64"] == outs["int8"], axis=1)))
         primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
 
-    if not args.no_add:
-        rec_add = add32_latency(keys, dev, args.form)
-    else:
-        rec_add = None
+    tuner = None
+    if not args.no_autotune and not (args.no_add and args.no_mixed):
+        from paper_2101_03403_amd.autotune import Autotuner
+        tuner = Autotuner(keys)
+    rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
+    rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -262,6 +303,11 @@ def main():
     }
     if rec_add is not None:
         rec["add32"] = rec_add
+    if rec_mix is not None:
+        rec["mixed_stream"] = rec_mix
+    if tuner is not None:
+        rec["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner.measurements.get(b)}
+                           for b, c in sorted(tuner.table.items())}
     if "identical_outputs_fft64_vs_int8" in primary:
         rec["identical_outputs_fft64_vs_int8"] = primary["identical_outputs_fft64_vs_int8"]
     print(json.dumps(rec), flush=True)

@@ -188,6 +188,21 @@ int cemu_export_keys(const cemu_secret_key *sk, const cemu_cloud_key *ck, int32_
 void cemu_free_secret_key(cemu_secret_key *sk);
 void cemu_free_cloud_key(cemu_cloud_key *ck);
 
+/* Launch configuration of the blind-rotation kernels (per cloud key).
+ * int8_waves: waves per workgroup of the int8-MFMA kernel, 4 or 8 (default 8).
+ * fft_gates_per_wg: gates per workgroup of the FFT64 kernel, 4 (one wave per
+ *   SIMD, 512 registers each) or 8 (two waves per SIMD; default).
+ * The tuning only changes speed, never results. cemu_set_tuning returns
+ * CEMU_ERR_PARAM for unsupported values and leaves the key unchanged.
+ * Callers: the autotuner (paper_2101_03403_amd/autotune.py). */
+typedef struct cemu_tuning {
+    int32_t int8_waves;
+    int32_t fft_gates_per_wg;
+    int32_t reserved[6];
+} cemu_tuning;
+int cemu_get_tuning(const cemu_cloud_key *ck, cemu_tuning *t);
+int cemu_set_tuning(cemu_cloud_key *ck, const cemu_tuning *t);
+
 /* Kernel timing with HIP events. While enabled, every kernel the library
  * launches for this cloud key is bracketed by a pair of hipEvents recorded on
  * the same stream. cemu_profile_read waits for the recorded events, returns

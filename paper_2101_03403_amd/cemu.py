@@ -37,6 +37,10 @@ class CemuError(RuntimeError):
         self.code = code
 
 
+class Tuning(C.Structure):
+    _fields_ = [("int8_waves", C.c_int32), ("fft_gates_per_wg", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
 class Params(C.Structure):
     _fields_ = [("n", C.c_int32), ("N", C.c_int32), ("k", C.c_int32), ("l", C.c_int32),
                 ("bgbit", C.c_int32), ("t", C.c_int32), ("basebit", C.c_int32), ("reserved", C.c_int32),
@@ -51,7 +55,7 @@ EXPORTED = [
     "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates",
     "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
-    "cemu_profile_enable", "cemu_profile_read",
+    "cemu_profile_enable", "cemu_profile_read", "cemu_get_tuning", "cemu_set_tuning",
 ]
 PROFILE_KINDS = ["lincomb_modswitch", "blind_rotate_int8", "blind_rotate_fft64", "key_switch"]
 
@@ -87,6 +91,8 @@ def lib() -> C.CDLL:
     L.cemu_free_secret_key.restype = None
     L.cemu_free_cloud_key.argtypes = [vp]
     L.cemu_free_cloud_key.restype = None
+    L.cemu_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+    L.cemu_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
     L.cemu_profile_enable.argtypes = [vp, C.c_int]
     L.cemu_profile_read.argtypes = [vp, vp, vp]
     L.cemu_last_error.restype = C.c_char_p
@@ -197,6 +203,20 @@ class Keys:
         _check(lib().cemu_export_keys(self.sk, self.ck, _np_ptr(lwe), _np_ptr(tlwe),
                                       _np_ptr(bka) if bk else None, _np_ptr(ksa) if ksk else None))
         return {"lwe_key": lwe, "tlwe_key": tlwe, "bk": bka, "ksk": ksa}
+
+
+def get_tuning(keys: Keys) -> dict:
+    t = Tuning()
+    _check(lib().cemu_get_tuning(keys.ck, C.byref(t)))
+    return {"int8_waves": t.int8_waves, "fft_gates_per_wg": t.fft_gates_per_wg}
+
+
+def set_tuning(keys: Keys, int8_waves: int | None = None, fft_gates_per_wg: int | None = None):
+    cur = get_tuning(keys)
+    t = Tuning()
+    t.int8_waves = cur["int8_waves"] if int8_waves is None else int8_waves
+    t.fft_gates_per_wg = cur["fft_gates_per_wg"] if fft_gates_per_wg is None else fft_gates_per_wg
+    _check(lib().cemu_set_tuning(keys.ck, C.byref(t)))
 
 
 def profile_enable(keys: Keys, enable: bool = True):

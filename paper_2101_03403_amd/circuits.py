@@ -323,9 +323,11 @@ class Program:
         }
         return self
 
-    def run(self, keys, pool, form="fft64", stream=None, profile_levels=None):
+    def run(self, keys, pool, form="fft64", stream=None, profile_levels=None, tuner=None):
         """Enqueue the whole program on `stream`: constants, then per level the
-        NOTs it needs and one batched gate launch (gather/scatter in `pool`)."""
+        NOTs it needs and one batched gate launch (gather/scatter in `pool`).
+        With an autotuner, each level's form and tiles are the tuner's choice
+        for that level's width."""
         import torch
         if self._dev is None:
             self.to_device(pool.device)
@@ -340,23 +342,25 @@ class Program:
             if profile_levels is not None:
                 ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 ev[0].record(stream)
-            cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=form, stream=stream)
+            f = tuner.apply(int(ops.shape[0])) if tuner is not None else form
+            cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=f, stream=stream)
             if ev is not None:
                 ev[1].record(stream)
                 profile_levels.append(ev)
         if d["tail"][0].shape[0]:
             cemu.lwe_not(n, pool, d["tail"][0], pool, d["tail"][1], stream=stream)
 
-    def capture(self, keys, pool, form="fft64"):
+    def capture(self, keys, pool, form="fft64", tuner=None):
         """Capture the level sequence as one hipGraph (after an eager run has
-        sized the library's workspaces). Returns the torch graph object."""
+        sized the library's workspaces and, with a tuner, tuned every level
+        width). Returns the torch graph object."""
         import torch
         stream = torch.cuda.Stream()
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.stream(stream):
             with torch.cuda.graph(g, stream=stream):
-                self.run(keys, pool, form=form, stream=torch.cuda.current_stream())
+                self.run(keys, pool, form=form, stream=torch.cuda.current_stream(), tuner=tuner)
         torch.cuda.synchronize()
         self._graph = g
         return g

@@ -20,8 +20,7 @@
 // from that order, so no bit reversal is ever done. Key spectra are stored in
 // the same (slot, lane) order.
 //
-// One wave per gate, FG = 8 gates per workgroup (two waves per SIMD, which
-// measured faster than one wave per SIMD with twice the registers): each wave keeps its
+// One wave per gate, FG = 8 (default) or 4 gates per workgroup: each wave keeps its
 // accumulator (2 x N u32) and its FFT transpose scratch in LDS; the key
 // spectra of one digit row (16 KiB) are staged in LDS once per workgroup,
 // prefetched through registers one row ahead.
@@ -256,15 +255,17 @@ __global__ __launch_bounds__(64) void bk_fft_prepare_kernel(const uint8_t *__res
     for (int s = 0; s < 8; ++s) dst[s * 64 + lane] = x[s];
 }
 
-constexpr int FG = 8;                      // gates (waves) per workgroup: two waves per SIMD
-constexpr int F_THREADS = 64 * FG;
 constexpr int STAGE_D2 = 2 * FH;           // key spectra of one digit row: (q, slot, lane)
-constexpr int F_PRE = STAGE_D2 / F_THREADS; // d2 per thread per stage
 
-__global__ __launch_bounds__(F_THREADS, 1) void br_fft_kernel(const d2 *__restrict__ spec,
-                                                              const uint16_t *__restrict__ bars, int32_t n, int64_t B,
-                                                              uint32_t *__restrict__ ext)
+// FG = gates (waves) per workgroup: 8 (two waves per SIMD, 256 registers
+// each) or 4 (one wave per SIMD, 512 registers).
+template <int FG>
+__global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict__ spec,
+                                                           const uint16_t *__restrict__ bars, int32_t n, int64_t B,
+                                                           uint32_t *__restrict__ ext)
 {
+    constexpr int F_THREADS = 64 * FG;
+    constexpr int F_PRE = STAGE_D2 / F_THREADS;   // d2 per thread per stage
     __shared__ uint32_t acc_all[FG][2][FN];
     __shared__ d2 scr_all[FG][SCR];
     __shared__ d2 kst[STAGE_D2];               // key spectra of the current digit row
@@ -398,9 +399,11 @@ int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t 
         if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("bk_fft_prepare launch: ") + hipGetErrorString(e));
     }
     if (B > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
-    const int64_t blocks = (B + FG - 1) / FG;
-    hipLaunchKernelGGL(br_fft_kernel, dim3((unsigned)blocks), dim3(F_THREADS), 0, s,
-                       reinterpret_cast<const d2 *>(ck->d_bkfft), bars, n, B, ext);
+    const d2 *spec = reinterpret_cast<const d2 *>(ck->d_bkfft);
+    if (ck->tuning.fft_gates_per_wg == 4)
+        hipLaunchKernelGGL(br_fft_kernel<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, spec, bars, n, B, ext);
+    else
+        hipLaunchKernelGGL(br_fft_kernel<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), 0, s, spec, bars, n, B, ext);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("br_fft_kernel launch: ") + hipGetErrorString(e));
     return CEMU_OK;

@@ -29,7 +29,6 @@
 // the step's running sum in registers until the accumulators are updated.
 #include <hip/hip_runtime.h>
 
-#include <cstdlib>
 #include <type_traits>
 
 #include "cemu_kernels.h"
@@ -264,18 +263,6 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
     }
 }
 
-// Waves per workgroup: 8 (two per SIMD, a quarter of the rows of one
-// component each; the faster choice on MI355X) or 4 (one per SIMD, half the
-// rows each). CEMU_BR_INT8_WAVES=4 selects the latter.
-int br_int8_waves(int, int64_t)
-{
-    static const int env = [] {
-        const char *e = std::getenv("CEMU_BR_INT8_WAVES");
-        return e ? std::atoi(e) : 0;
-    }();
-    return env == 4 ? 4 : 8;
-}
-
 template <int N, int WAVES>
 int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
 {
@@ -291,7 +278,7 @@ int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, ui
 {
     const int64_t blocks = (B + BR_G - 1) / BR_G;
     if (blocks > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
-    const int waves = br_int8_waves(ck->p.N, B);
+    const int waves = ck->tuning.int8_waves;   // 4 or 8 (validated by cemu_set_tuning)
     int rc;
     if (ck->p.N == 1024) rc = waves == 8 ? launch_shape<1024, 8>(ck, bars, B, ext, s) : launch_shape<1024, 4>(ck, bars, B, ext, s);
     else if (ck->p.N == 512) rc = waves == 8 ? launch_shape<512, 8>(ck, bars, B, ext, s) : launch_shape<512, 4>(ck, bars, B, ext, s);

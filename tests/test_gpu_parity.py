@@ -330,3 +330,42 @@ def test_program_int8_form_small(std, dev):
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
         assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
+
+
+def test_tuning_variants_give_identical_results(std, dev):
+    """Every launch configuration the autotuner may pick computes the same
+    ciphertexts (ragged batch of 45 gates)."""
+    lk, ok = std
+    B = 45
+    ops, a, b = W.gate_batch(B, seed=91)
+    c1 = lk.encrypt(a, seed=92)
+    c2 = lk.encrypt(b, seed=92, first_index=B)
+    ref = None
+    saved = cemu.get_tuning(lk)
+    try:
+        for form, tun in [("fft64", {"fft_gates_per_wg": 8}), ("fft64", {"fft_gates_per_wg": 4}),
+                          ("int8", {"int8_waves": 8}), ("int8", {"int8_waves": 4})]:
+            cemu.set_tuning(lk, **tun)
+            ext, out = run_gates(lk, ops, c1, c2, dev, form=form)
+            if ref is None:
+                ref = (ext, out)
+            assert np.array_equal(ext, ref[0]) and np.array_equal(out, ref[1]), (form, tun)
+        with pytest.raises(cemu.CemuError):
+            cemu.set_tuning(lk, int8_waves=6)
+    finally:
+        cemu.set_tuning(lk, **saved)
+    oext, _ = O.bootstrap_batch(ok, ops[:4].astype(np.int32), c1[:4], c2[:4], want_out=False)
+    assert np.array_equal(ref[0][:4], oext)
+
+
+def test_autotuner_picks_and_caches(std, dev, tmp_path):
+    from paper_2101_03403_amd.autotune import Autotuner, bucket
+    lk, _ = std
+    path = str(tmp_path / "tune.json")
+    t = Autotuner(lk, cache_path=path, reps=1)
+    form, tun = t.best(100)
+    assert bucket(100) == 128 and form in ("fft64", "int8")
+    assert len(t.measurements[128]) == 4
+    t2 = Autotuner(lk, cache_path=path)
+    assert t2.best(120) == (form, tun)      # same bucket, from the file, no measuring
+    assert t2.measurements == {}
