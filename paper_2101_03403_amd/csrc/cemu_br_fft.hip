@@ -158,10 +158,11 @@ __device__ __forceinline__ void xpose_hi(d2 (&x)[8], d2 *scr, int lane)
 
 // Twiddle bases of one lane (W = exp(-2 pi i / 512)).
 struct Tw {
+    d2 tw;    // w^lane, w = exp(i pi / N): the per-lane part of the twist
     d2 f1;    // W^lane                       (forward pass 1, powers over slot)
     d2 f2;    // W^(8 (lane & 7))             (forward pass 2; conj for inverse pass 1)
-    d2 i2c;   // W^-((lane & 7) (lane >> 3))  (inverse pass 2, constant factor)
-    d2 i2b;   // W^-(8 (lane >> 3))           (inverse pass 2, power base)
+    d2 i2c;   // W^-((lane & 7) (lane >> 3)) w^-(lane & 7) / (N/2)  (inverse pass 2 constant, with untwist part and scale)
+    d2 i2b;   // W^-(8 (lane >> 3)) w^-8        (inverse pass 2, power base)
 };
 
 // Hide a value's provenance from the optimiser so that products of it
@@ -181,16 +182,23 @@ __device__ __forceinline__ Tw make_tw(int lane)
     Tw t;
     t.f1 = cexp_unit(two_pi_over * lane);
     t.f2 = cexp_unit(two_pi_over * (8 * (lane & 7)));
-    t.i2c = cexp_unit(-two_pi_over * ((lane & 7) * (lane >> 3)));
-    t.i2b = cexp_unit(-two_pi_over * (8 * (lane >> 3)));
+    t.tw = cexp_unit(3.14159265358979323846 / FN * lane);
+    // the untwist w^-(8 j1 + j0) of the destination lane (j1, j0) after the
+    // following transpose = w^-j0 * (w^-8)^j1: a power series in the slot j1
+    t.i2c = cmul(cexp_unit(-two_pi_over * ((lane & 7) * (lane >> 3))),
+                 cexp_unit(-3.14159265358979323846 / FN * (lane & 7))) * (1.0 / FH);
+    t.i2b = cmul(cexp_unit(-two_pi_over * (8 * (lane >> 3))), cexp_unit(-3.14159265358979323846 / FN * 8));
     return t;
 }
 
-// Forward FFT_512: in x[m] = z[lane + 64 m]; out slot k2 of lane 8 k0 + k1 = Z[k0 + 8 k1 + 64 k2].
+// Forward twisted FFT_512: in x[m] = P-fold[lane + 64 m] * w^(64 m) (the
+// per-slot part of the twist); the per-lane part w^lane commutes with the
+// first length-8 DFT and is applied with its twiddles. Out: slot k2 of lane
+// 8 k0 + k1 = Z[k0 + 8 k1 + 64 k2].
 __device__ __forceinline__ void fft_fwd(d2 (&x)[8], d2 *scr, int lane, const Tw &t)
 {
     dft8<false>(x);                 // lane (j1, j0): over j2 -> k0
-    twiddle_pow(x, t.f1);           // W^((8 j1 + j0) k0)
+    twiddle_pow(x, t.tw, t.f1);     // w^lane * W^((8 j1 + j0) k0): twist (per-lane part) + twiddle
     xpose_hi(x, scr, lane);         // lane (k0, j0), slot j1
     __builtin_amdgcn_sched_barrier(0);
     dft8<false>(x);                 // over j1 -> k1
@@ -200,7 +208,9 @@ __device__ __forceinline__ void fft_fwd(d2 (&x)[8], d2 *scr, int lane, const Tw 
     dft8<false>(x);                 // over j0 -> k2
 }
 
-// Inverse (unscaled): the data movement of fft_fwd run backwards.
+// Inverse: the data movement of fft_fwd run backwards; the per-lane untwist
+// w^-lane and the 1/(N/2) scale ride on the last twiddle (they commute with the
+// final length-8 DFT); the caller multiplies slot m by conj(w^(64 m)).
 __device__ __forceinline__ void fft_inv(d2 (&x)[8], d2 *scr, int lane, const Tw &t)
 {
     dft8<true>(x);                  // lane (k0, k1): over k2 -> j0
@@ -233,7 +243,6 @@ __global__ __launch_bounds__(64) void bk_fft_prepare_kernel(const uint8_t *__res
     const int64_t poly = blockIdx.x;            // (i*6 + r)*2 + q
     const uint8_t *base = bk8 + poly * 4 * (2 * FN);
     const Tw t = make_tw(lane);
-    const d2 wl = cexp_unit(3.14159265358979323846 / FN * lane);
     d2 x[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -247,7 +256,7 @@ __global__ __launch_bounds__(64) void bk_fft_prepare_kernel(const uint8_t *__res
             for (int k = 3; k >= 0; --k) val = (val << 8) + (uint32_t)(int32_t)(int8_t)base[k * (2 * FN) + u];
             v[h] = (double)(int32_t)val;
         }
-        x[m] = cmul(d2{v[0], v[1]}, cmul(wl, twist_slot(m)));
+        x[m] = cmul(d2{v[0], v[1]}, twist_slot(m));
     }
     fft_fwd(x, scr, lane, t);
     d2 *dst = spec + poly * FH;
@@ -276,8 +285,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
     d2 *scr = scr_all[wave];
     const uint16_t *bar = bars + (live ? g : 0) * (int64_t)(n + 1);
     const Tw t0 = make_tw(lane);
-    const d2 wl0 = cexp_unit(3.14159265358979323846 / FN * lane);
-    Tw t = t0; d2 wl = wl0;
+    Tw t = t0;
 
     // ACC = (0, X^{-bbar} v)
     const uint32_t bb = live ? bar[n] : 0u;
@@ -294,7 +302,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
     for (int i = 0; i < n; ++i) {
         const uint32_t a = a_next;
         if (live && i + 1 < n) a_next = bar[i + 1];
-        launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b); launder(wl);
+        launder(t.tw); launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b);
         d2 outA[8], outB[8];
         static_for<0, 8>([&](auto sI) {
             outA[decltype(sI)::value] = d2{0.0, 0.0};
@@ -339,7 +347,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
                     constexpr int m = decltype(mI)::value;
                     const double lo = (double)((int32_t)((dlo[m] >> sh) & 127u) - 64);
                     const double hi = (double)((int32_t)((dhi[m] >> sh) & 127u) - 64);
-                    x[m] = cmul(d2{lo, hi}, cmul(wl, twist_slot(m)));
+                    x[m] = cmul(d2{lo, hi}, twist_slot(m));
                 });
                 __builtin_amdgcn_sched_barrier(0);
                 fft_fwd(x, scr, lane, t);
@@ -358,7 +366,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
             fft_inv(x, scr, lane, t);
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
-                const d2 y = cmul(x[m], cconj(cmul(wl, twist_slot(m)))) * (1.0 / FH);
+                const d2 y = cmul(x[m], cconj(twist_slot(m)));
                 const int j = lane + 64 * m;
                 dst[j] += (uint32_t)(int64_t)rint(y.x);
                 dst[j + FH] += (uint32_t)(int64_t)rint(y.y);
