@@ -43,10 +43,10 @@ FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
 # plain 1 GiB copy); summary and commands in profiles/. Valid only while the
 # kernel source is the one profiled (sha256 prefix), else reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "c1c32a57930cbcc8",
-              "bytes": 970_992 * 1024 * 2 + 16_416 * 1024, "batch": 4096},
-    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "d6b46fb8e0bdd172",
-             "bytes": 245_924 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "d095ed9b85788bcc",
+              "bytes": 488_564 * 1024 * 2 + 19_472 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "65afeedf9381a23e",
+             "bytes": 245_914 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
 }
 
 
