@@ -191,9 +191,16 @@ void cemu_free_cloud_key(cemu_cloud_key *ck);
 /* Launch configuration of the blind-rotation kernels (per cloud key).
  * int8_waves: waves per workgroup of the int8-MFMA kernel, 4 or 8 (default 8).
  * fft_gates_per_wg: gates per workgroup of the FFT64 kernel, 4 (one wave per
- *   SIMD, 512 registers each) or 8 (two waves per SIMD; default).
- * The tuning only changes speed, never results. cemu_set_tuning returns
- * CEMU_ERR_PARAM for unsupported values and leaves the key unchanged.
+ *   SIMD, 512 registers each) or 8 (two waves per SIMD; default), or 1: the
+ *   latency kernel, one gate per workgroup of 6 waves (one wave per gadget
+ *   digit row), for batches too narrow to fill the GPU.
+ * The int8 choices and FFT64 choices 4/8 only change speed, never results.
+ * FFT64 choice 1 adds the six digit-row products in another rounding order;
+ * since every product is an integer polynomial, all FFT64 choices return the
+ * same ciphertexts whenever the transform error stays below half a unit
+ * (which is what the parity tests check against the exact oracle).
+ * cemu_set_tuning returns CEMU_ERR_PARAM for unsupported values and leaves the
+ * key unchanged.
  * Callers: the autotuner (paper_2101_03403_amd/autotune.py). */
 typedef struct cemu_tuning {
     int32_t int8_waves;

@@ -2,7 +2,8 @@
 
 For a cloud key and a batch size it measures every candidate launch
 configuration -- product form (FP64-FFT or int8-MFMA) x its tile choice
-(FFT: 8 or 4 gates per workgroup; int8: 8 or 4 waves per workgroup) -- on a
+(FFT: 8 or 4 gates per workgroup, or the one-gate-per-workgroup latency
+kernel; int8: 8 or 4 waves per workgroup) -- on a
 synthetic batch of that size, keeps the fastest, and caches the choice per
 (parameter set, batch-size bucket) in memory and optionally in a JSON file.
 Kernel timing uses the library's own HIP-event profiling (cemu_profile_*),
@@ -24,6 +25,7 @@ from . import cemu
 CANDIDATES = (
     ("fft64", {"fft_gates_per_wg": 8}),
     ("fft64", {"fft_gates_per_wg": 4}),
+    ("fft64", {"fft_gates_per_wg": 1}),
     ("int8", {"int8_waves": 8}),
     ("int8", {"int8_waves": 4}),
 )

@@ -20,10 +20,18 @@
 // from that order, so no bit reversal is ever done. Key spectra are stored in
 // the same (slot, lane) order.
 //
-// One wave per gate, FG = 8 (default) or 4 gates per workgroup: each wave keeps its
-// accumulator (2 x N u32) and its FFT transpose scratch in LDS; the key
-// spectra of one digit row (16 KiB) are staged in LDS once per workgroup,
-// prefetched through registers one row ahead.
+// Throughput kernel: one wave per gate, FG = 8 (default) or 4 gates per
+// workgroup: each wave keeps its accumulator (2 x N u32) and its FFT transpose
+// scratch in LDS; the key spectra of one digit row (16 KiB) are staged in LDS
+// once per workgroup, prefetched through registers one row ahead.
+//
+// Latency kernel (narrow batches): one gate per workgroup of 6 waves, one
+// wave per gadget digit, so the 6 forward transforms of a step run side by
+// side; each digit wave multiplies its spectrum by its own two key spectra
+// (prefetched into registers a step ahead), the partial products meet in
+// LDS, and two waves sum them in a fixed order and run the two inverse
+// transforms. A step then costs about three transform latencies instead of
+// eight.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -51,6 +59,18 @@ constexpr uint32_t kDigitOffset = 0x81020400u;   // see cemu_br_int8.hip
 
 __device__ __forceinline__ d2 cmul(d2 a, d2 b) { return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ d2 cconj(d2 a) { return d2{a.x, -a.y}; }
+
+// Nearest integer of y reduced mod 2^32, for |y| < 2^51: adding 1.5 * 2^52
+// lands in the binade [2^52, 2^53) whose spacing is 1, so the addition itself
+// rounds (to nearest, ties to even, as rint does) and the low mantissa bits
+// hold 2^51 + rint(y), whose low 32 bits are rint(y) mod 2^32. One FP64 add
+// instead of rint plus a double -> int64 conversion. The bound holds with a
+// wide margin: |y| <= 6 * N * 64 * 2^31 only for adversarial keys, and the
+// centred random key coefficients keep sums near 2^42.
+__device__ __forceinline__ uint32_t round_mod32(double y)
+{
+    return (uint32_t)__double_as_longlong(y + 6755399441055744.0);
+}
 
 __device__ __forceinline__ d2 cexp_unit(double theta)
 {
@@ -368,8 +388,8 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
                 constexpr int m = decltype(mI)::value;
                 const d2 y = cmul(x[m], cconj(twist_slot(m)));
                 const int j = lane + 64 * m;
-                dst[j] += (uint32_t)(int64_t)rint(y.x);
-                dst[j + FH] += (uint32_t)(int64_t)rint(y.y);
+                dst[j] += round_mod32(y.x);
+                dst[j + FH] += round_mod32(y.y);
             });
         };
         finish(outA, acc[0]);
@@ -391,6 +411,117 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
     }
 }
 
+constexpr int LAT_WAVES = 6;   // one wave per digit row (2 components x l = 3)
+
+__global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 *__restrict__ spec,
+                                                                      const uint16_t *__restrict__ bars, int32_t n,
+                                                                      uint32_t *__restrict__ ext)
+{
+    __shared__ uint32_t acc[2][FN];
+    __shared__ d2 scr_all[LAT_WAVES][SCR];
+    __shared__ d2 part[2][LAT_WAVES][FH];     // partial products (output q, digit row p, slot*64 + lane)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int p = tid >> 6;                    // digit row of this wave: component c, digit jj
+    const int c = p / 3, jj = p - 3 * c;
+    const uint32_t sh = (uint32_t)(32 - 7 * (jj + 1));
+    const int64_t g = blockIdx.x;              // the grid has exactly one workgroup per gate
+    d2 *scr = scr_all[p];
+    const uint16_t *bar = bars + g * (int64_t)(n + 1);
+    const Tw t0 = make_tw(lane);
+    Tw t = t0;
+
+    // ACC = (0, X^{-bbar} v)
+    const uint32_t bb = bar[n];
+    for (int m = tid; m < FN; m += 64 * LAT_WAVES) {
+        const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * FN - 1);
+        acc[0][m] = 0u;
+        acc[1][m] = tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+    }
+    // key spectra of (step 0, row p) for both outputs, in (q, slot, lane) order
+    d2 kq[16];
+    {
+        const d2 *src = spec + (int64_t)p * STAGE_D2 + lane;
+        static_for<0, 16>([&](auto kI) { kq[decltype(kI)::value] = src[decltype(kI)::value * 64]; });
+    }
+    __syncthreads();
+
+    uint32_t a_next = bar[0];
+    for (int i = 0; i < n; ++i) {
+        const uint32_t a = a_next;
+        if (i + 1 < n) a_next = bar[i + 1];
+        launder(t.tw); launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b);
+        // digit jj of D = X^a ACC_c - ACC_c at this lane's 16 coefficients
+        d2 x[8];
+        static_for<0, 8>([&](auto mI) {
+            constexpr int m = decltype(mI)::value;
+            double v2[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const uint32_t j = (uint32_t)(lane + 64 * m + h * FH);
+                const uint32_t tt = (j - a) & (uint32_t)(2 * FN - 1);
+                uint32_t v = acc[c][tt & (uint32_t)(FN - 1)];
+                v = (tt & (uint32_t)FN) ? 0u - v : v;
+                const uint32_t d = v - acc[c][j] + kDigitOffset;
+                v2[h] = (double)((int32_t)((d >> sh) & 127u) - 64);
+            }
+            x[m] = cmul(d2{v2[0], v2[1]}, twist_slot(m));
+        });
+        __builtin_amdgcn_sched_barrier(0);
+        fft_fwd(x, scr, lane, t);
+        __builtin_amdgcn_sched_barrier(0);
+        // partial products of this digit row with the two key spectra
+        d2 own[8];
+        static_for<0, 8>([&](auto sI) {
+            constexpr int sl = decltype(sI)::value;
+            const d2 pa = cmul(x[sl], kq[sl]);
+            const d2 pb = cmul(x[sl], kq[8 + sl]);
+            if (p == 0) own[sl] = pa; else part[0][p][sl * 64 + lane] = pa;
+            if (p == 1) own[sl] = pb; else part[1][p][sl * 64 + lane] = pb;
+        });
+        {   // prefetch the next step's key spectra (past the last step: step 0, unused)
+            const int ni = i + 1 < n ? i + 1 : 0;
+            const d2 *src = spec + ((int64_t)ni * 6 + p) * STAGE_D2 + lane;
+            static_for<0, 16>([&](auto kI) { kq[decltype(kI)::value] = src[decltype(kI)::value * 64]; });
+        }
+        __syncthreads();   // partial products visible
+        if (p < 2) {
+            // output q = p: sum the six rows in row order, inverse transform,
+            // untwist, round and accumulate into ACC_q
+            d2 y[8];
+            static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] = d2{0.0, 0.0}; });
+#pragma unroll
+            for (int w = 0; w < LAT_WAVES; ++w) {
+                if (w == p) {
+                    static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] += own[decltype(sI)::value]; });
+                } else {
+                    const d2 *src = &part[p][w][lane];
+                    static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] += src[decltype(sI)::value * 64]; });
+                }
+            }
+            fft_inv(y, scr, lane, t);
+            uint32_t *dst = acc[p];
+            static_for<0, 8>([&](auto mI) {
+                constexpr int m = decltype(mI)::value;
+                const d2 z = cmul(y[m], cconj(twist_slot(m)));
+                const int j = lane + 64 * m;
+                dst[j] += round_mod32(z.x);
+                dst[j + FH] += round_mod32(z.y);
+            });
+        }
+        __syncthreads();   // ACC updated
+    }
+
+    // sample extraction
+    uint32_t *e = ext + g * (FN + 1);
+    for (int j = tid; j <= FN; j += 64 * LAT_WAVES) {
+        uint32_t v;
+        if (j == 0) v = acc[0][0];
+        else if (j == FN) v = acc[1][0];
+        else v = 0u - acc[0][FN - j];
+        e[j] = v;
+    }
+}
+
 }  // namespace
 
 int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
@@ -408,7 +539,10 @@ int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t 
     }
     if (B > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
     const d2 *spec = reinterpret_cast<const d2 *>(ck->d_bkfft);
-    if (ck->tuning.fft_gates_per_wg == 4)
+    if (B == 0) return CEMU_OK;
+    if (ck->tuning.fft_gates_per_wg == 1)
+        hipLaunchKernelGGL(br_fft_lat_kernel, dim3((unsigned)B), dim3(64 * LAT_WAVES), 0, s, spec, bars, n, ext);
+    else if (ck->tuning.fft_gates_per_wg == 4)
         hipLaunchKernelGGL(br_fft_kernel<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, spec, bars, n, B, ext);
     else
         hipLaunchKernelGGL(br_fft_kernel<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), 0, s, spec, bars, n, B, ext);

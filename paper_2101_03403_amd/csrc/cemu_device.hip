@@ -434,8 +434,8 @@ int cemu_set_tuning(cemu_cloud_key *ck, const cemu_tuning *t)
     clear_error();
     if (!ck || !t) return fail(CEMU_ERR_NULL, "NULL argument");
     if (t->int8_waves != 4 && t->int8_waves != 8) return fail(CEMU_ERR_PARAM, "int8_waves must be 4 or 8");
-    if (t->fft_gates_per_wg != 4 && t->fft_gates_per_wg != 8)
-        return fail(CEMU_ERR_PARAM, "fft_gates_per_wg must be 4 or 8");
+    if (t->fft_gates_per_wg != 1 && t->fft_gates_per_wg != 4 && t->fft_gates_per_wg != 8)
+        return fail(CEMU_ERR_PARAM, "fft_gates_per_wg must be 1, 4 or 8");
     std::lock_guard<std::mutex> lock(ck->mu);
     ck->tuning = *t;
     return CEMU_OK;

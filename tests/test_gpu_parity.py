@@ -239,16 +239,22 @@ def to_i32(x):
     return x.astype(np.int64) - ((x >> 31).astype(np.int64) << 32)
 
 
-@pytest.mark.parametrize("B", [37, 512])
-def test_fft_form_decrypts_and_phase_error(std, dev, B):
-    """FP64-FFT form: every decryption exact; extracted samples compared with
-    the oracle on sampled gates (raw words and decrypted phase)."""
+@pytest.mark.parametrize("B,fg", [(37, 8), (512, 8), (37, 1), (300, 1)])
+def test_fft_form_decrypts_and_phase_error(std, dev, B, fg):
+    """FP64-FFT form (fg = gates per workgroup; 1 is the latency kernel):
+    every decryption exact; extracted samples compared with the oracle on
+    sampled gates (raw words and decrypted phase)."""
     lk, ok = std
-    say(f"[gpu] fft64 form B={B}")
+    say(f"[gpu] fft64 form B={B} fft_gates_per_wg={fg}")
     ops, a, b = W.gate_batch(B, seed=51 + B)
     c1 = lk.encrypt(a, seed=61)
     c2 = lk.encrypt(b, seed=61, first_index=B)
-    ext, out = run_gates(lk, ops, c1, c2, dev, form="fft64")
+    saved = cemu.get_tuning(lk)
+    try:
+        cemu.set_tuning(lk, fft_gates_per_wg=fg)
+        ext, out = run_gates(lk, ops, c1, c2, dev, form="fft64")
+    finally:
+        cemu.set_tuning(lk, **saved)
     truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
     want = np.array([truth[int(o)](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
     assert np.array_equal(lk.decrypt(out), want)
@@ -334,7 +340,10 @@ def test_program_int8_form_small(std, dev):
 
 def test_tuning_variants_give_identical_results(std, dev):
     """Every launch configuration the autotuner may pick computes the same
-    ciphertexts (ragged batch of 45 gates)."""
+    ciphertexts (ragged batch of 45 gates). The FFT64 latency kernel sums in
+    another order; it agrees because the form's error stays below half a
+    unit, so every product rounds to the exact integer (checked against the
+    oracle below)."""
     lk, ok = std
     B = 45
     ops, a, b = W.gate_batch(B, seed=91)
@@ -344,6 +353,7 @@ def test_tuning_variants_give_identical_results(std, dev):
     saved = cemu.get_tuning(lk)
     try:
         for form, tun in [("fft64", {"fft_gates_per_wg": 8}), ("fft64", {"fft_gates_per_wg": 4}),
+                          ("fft64", {"fft_gates_per_wg": 1}),
                           ("int8", {"int8_waves": 8}), ("int8", {"int8_waves": 4})]:
             cemu.set_tuning(lk, **tun)
             ext, out = run_gates(lk, ops, c1, c2, dev, form=form)
@@ -352,6 +362,8 @@ def test_tuning_variants_give_identical_results(std, dev):
             assert np.array_equal(ext, ref[0]) and np.array_equal(out, ref[1]), (form, tun)
         with pytest.raises(cemu.CemuError):
             cemu.set_tuning(lk, int8_waves=6)
+        with pytest.raises(cemu.CemuError):
+            cemu.set_tuning(lk, fft_gates_per_wg=2)
     finally:
         cemu.set_tuning(lk, **saved)
     oext, _ = O.bootstrap_batch(ok, ops[:4].astype(np.int32), c1[:4], c2[:4], want_out=False)
@@ -365,7 +377,7 @@ def test_autotuner_picks_and_caches(std, dev, tmp_path):
     t = Autotuner(lk, cache_path=path, reps=1)
     form, tun = t.best(100)
     assert bucket(100) == 128 and form in ("fft64", "int8")
-    assert len(t.measurements[128]) == 4
+    assert len(t.measurements[128]) == 5
     t2 = Autotuner(lk, cache_path=path)
     assert t2.best(120) == (form, tun)      # same bucket, from the file, no measuring
     assert t2.measurements == {}
