@@ -412,14 +412,23 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
 }
 
 constexpr int LAT_WAVES = 6;   // one wave per digit row (2 components x l = 3)
+constexpr int LAT_EXT = 3 * FN; // negacyclic extension of one ACC component
 
+// Partial-product slot of (output q, digit row w): row q's own product for
+// output q stays in that wave's registers, so 10 of the 12 pairs need a slot.
+__device__ __forceinline__ int lat_slot(int q, int w) { return q == 0 ? w - 1 : 5 + (w == 0 ? 0 : w - 1); }
+
+// ACC component c is kept as its negacyclic extension E_c[k], k < 3N:
+// E[k] = ACC[k] for k mod 2N < N and -ACC[k mod N] otherwise, so that
+// (X^a ACC)_j = E[(j - a) mod 2N + ...] is one plain strided read for all
+// j = base + 64 s with base = (lane - a) mod 2N and s < 16.
 __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 *__restrict__ spec,
                                                                       const uint16_t *__restrict__ bars, int32_t n,
                                                                       uint32_t *__restrict__ ext)
 {
-    __shared__ uint32_t acc[2][FN];
+    __shared__ uint32_t accx[2][LAT_EXT];
     __shared__ d2 scr_all[LAT_WAVES][SCR];
-    __shared__ d2 part[2][LAT_WAVES][FH];     // partial products (output q, digit row p, slot*64 + lane)
+    __shared__ d2 part[10][FH];               // partial products (slot, slot*64 + lane)
     const int tid = threadIdx.x, lane = tid & 63;
     const int p = tid >> 6;                    // digit row of this wave: component c, digit jj
     const int c = p / 3, jj = p - 3 * c;
@@ -430,13 +439,23 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     const Tw t0 = make_tw(lane);
     Tw t = t0;
 
-    // ACC = (0, X^{-bbar} v)
+    // ACC = (0, X^{-bbar} v), written as its extension
     const uint32_t bb = bar[n];
-    for (int m = tid; m < FN; m += 64 * LAT_WAVES) {
-        const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * FN - 1);
-        acc[0][m] = 0u;
-        acc[1][m] = tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+    for (int k = tid; k < LAT_EXT; k += 64 * LAT_WAVES) {
+        const uint32_t m = (uint32_t)k & (uint32_t)(FN - 1);
+        const uint32_t tt = (m + bb) & (uint32_t)(2 * FN - 1);
+        const uint32_t v = tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+        accx[0][k] = 0u;
+        accx[1][k] = ((uint32_t)k & (uint32_t)FN) ? 0u - v : v;
     }
+    // the two output waves keep their component's own 16 coefficients
+    // (j = lane + 64 m + 512 h) in registers
+    uint32_t mine[16];
+    static_for<0, 16>([&](auto sI) {
+        constexpr int sl = decltype(sI)::value;
+        const uint32_t tt = ((uint32_t)(lane + 64 * sl) + bb) & (uint32_t)(2 * FN - 1);
+        mine[sl] = p == 1 ? (tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u) : 0u;
+    });
     // key spectra of (step 0, row p) for both outputs, in (q, slot, lane) order
     d2 kq[16];
     {
@@ -445,38 +464,35 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     }
     __syncthreads();
 
+    const uint32_t *ec = accx[c];
+    const uint32_t *own = ec + lane;
     uint32_t a_next = bar[0];
     for (int i = 0; i < n; ++i) {
         const uint32_t a = a_next;
         if (i + 1 < n) a_next = bar[i + 1];
         launder(t.tw); launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b);
         // digit jj of D = X^a ACC_c - ACC_c at this lane's 16 coefficients
+        const uint32_t *rot = ec + (((uint32_t)lane - a) & (uint32_t)(2 * FN - 1));
         d2 x[8];
         static_for<0, 8>([&](auto mI) {
             constexpr int m = decltype(mI)::value;
-            double v2[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const uint32_t j = (uint32_t)(lane + 64 * m + h * FH);
-                const uint32_t tt = (j - a) & (uint32_t)(2 * FN - 1);
-                uint32_t v = acc[c][tt & (uint32_t)(FN - 1)];
-                v = (tt & (uint32_t)FN) ? 0u - v : v;
-                const uint32_t d = v - acc[c][j] + kDigitOffset;
-                v2[h] = (double)((int32_t)((d >> sh) & 127u) - 64);
-            }
-            x[m] = cmul(d2{v2[0], v2[1]}, twist_slot(m));
+            const uint32_t d0 = rot[64 * m] - own[64 * m] + kDigitOffset;
+            const uint32_t d1 = rot[64 * m + FH] - own[64 * m + FH] + kDigitOffset;
+            const double lo = (double)((int32_t)((d0 >> sh) & 127u) - 64);
+            const double hi = (double)((int32_t)((d1 >> sh) & 127u) - 64);
+            x[m] = cmul(d2{lo, hi}, twist_slot(m));
         });
         __builtin_amdgcn_sched_barrier(0);
         fft_fwd(x, scr, lane, t);
         __builtin_amdgcn_sched_barrier(0);
         // partial products of this digit row with the two key spectra
-        d2 own[8];
+        d2 keep[8];
         static_for<0, 8>([&](auto sI) {
             constexpr int sl = decltype(sI)::value;
             const d2 pa = cmul(x[sl], kq[sl]);
             const d2 pb = cmul(x[sl], kq[8 + sl]);
-            if (p == 0) own[sl] = pa; else part[0][p][sl * 64 + lane] = pa;
-            if (p == 1) own[sl] = pb; else part[1][p][sl * 64 + lane] = pb;
+            if (p == 0) keep[sl] = pa; else part[lat_slot(0, p)][sl * 64 + lane] = pa;
+            if (p == 1) keep[sl] = pb; else part[lat_slot(1, p)][sl * 64 + lane] = pb;
         });
         {   // prefetch the next step's key spectra (past the last step: step 0, unused)
             const int ni = i + 1 < n ? i + 1 : 0;
@@ -485,27 +501,36 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
         }
         __syncthreads();   // partial products visible
         if (p < 2) {
-            // output q = p: sum the six rows in row order, inverse transform,
-            // untwist, round and accumulate into ACC_q
+            // output q = p: the six rows summed in row order, inverse transform,
+            // untwist, round, accumulate
             d2 y[8];
-            static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] = d2{0.0, 0.0}; });
+            {
+                const d2 *r0 = part[lat_slot(1, 0)] + lane, *r1 = part[lat_slot(0, 1)] + lane;
+                static_for<0, 8>([&](auto sI) {
+                    constexpr int sl = decltype(sI)::value;
+                    y[sl] = (p == 0 ? keep[sl] : r0[sl * 64]) + (p == 1 ? keep[sl] : r1[sl * 64]);
+                });
+            }
 #pragma unroll
-            for (int w = 0; w < LAT_WAVES; ++w) {
-                if (w == p) {
-                    static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] += own[decltype(sI)::value]; });
-                } else {
-                    const d2 *src = &part[p][w][lane];
-                    static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] += src[decltype(sI)::value * 64]; });
-                }
+            for (int w = 2; w < LAT_WAVES; ++w) {
+                const d2 *r = part[lat_slot(p, w)] + lane;
+                static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] += r[decltype(sI)::value * 64]; });
             }
             fft_inv(y, scr, lane, t);
-            uint32_t *dst = acc[p];
+            uint32_t *dst = accx[p] + lane;
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
                 const d2 z = cmul(y[m], cconj(twist_slot(m)));
-                const int j = lane + 64 * m;
-                dst[j] += round_mod32(z.x);
-                dst[j + FH] += round_mod32(z.y);
+                const uint32_t v0 = mine[m] + round_mod32(z.x);
+                const uint32_t v1 = mine[m + 8] + round_mod32(z.y);
+                mine[m] = v0;
+                mine[m + 8] = v1;
+                dst[64 * m] = v0;
+                dst[64 * m + FN] = 0u - v0;
+                dst[64 * m + 2 * FN] = v0;
+                dst[64 * m + FH] = v1;
+                dst[64 * m + FH + FN] = 0u - v1;
+                dst[64 * m + FH + 2 * FN] = v1;
             });
         }
         __syncthreads();   // ACC updated
@@ -515,9 +540,9 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     uint32_t *e = ext + g * (FN + 1);
     for (int j = tid; j <= FN; j += 64 * LAT_WAVES) {
         uint32_t v;
-        if (j == 0) v = acc[0][0];
-        else if (j == FN) v = acc[1][0];
-        else v = 0u - acc[0][FN - j];
+        if (j == 0) v = accx[0][0];
+        else if (j == FN) v = accx[1][0];
+        else v = 0u - accx[0][FN - j];
         e[j] = v;
     }
 }
