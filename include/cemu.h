@@ -137,8 +137,8 @@ int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int
  *   ops:      device uint8_t [B], gate op codes (CEMU_NAND .. CEMU_ORYN)
  *   pool_in:  device uint32_t [P_in][n+1], ciphertext pool read by the gates
  *   ia, ib:   device int32_t [B], row of the first / second input in pool_in
- *   io:       device int32_t [B], row of pool_out receiving gate g's output;
- *             NULL means row g
+ *   io:       device int32_t [B], row of pool_out receiving gate g's output
+ *             (rows distinct within the batch); NULL means row g
  *   pool_out: device uint32_t [P_out][n+1]; may alias pool_in only if no
  *             output row is also an input row of this batch
  * Row indices are not range-checked on the device: the caller guarantees

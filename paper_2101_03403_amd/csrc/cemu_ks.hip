@@ -13,7 +13,11 @@
 // the int32 accumulators, as in the blind rotation.
 //
 // One wave per workgroup computes a 64-gate x 64-column tile: 4 x 4 MFMA
-// tiles of v_mfma_i32_16x16x64_i8. The one-hot A operand is generated in
+// tiles of v_mfma_i32_16x16x64_i8. Narrow batches (few tiles) also split the
+// K range over grid.z: each split Horner-combines the four limb products of
+// its K range (the recombination is linear), and the splits are summed into
+// an output pre-set to (0, b') with 32-bit integer atomics, which wrap exactly
+// like the single-pass sum and give the same result in any order. The one-hot A operand is generated in
 // registers from the rounded a'_i (one u32 per lane per M-tile and K-tile);
 // the B operand (key limbs) is pre-arranged at key generation in exactly the
 // per-lane order of the MFMA B operand, so each fragment load is one
@@ -43,7 +47,7 @@ constexpr int KS_T = 8;          // digits per coefficient (t)
 constexpr int KS_MT = 4;         // 16-gate M-tiles per wave
 constexpr int KS_NT = 4;         // 16-column N-tiles per wave
 
-template <int N>
+template <int N, bool SPLIT>
 __global__ __launch_bounds__(64) void ks_mfma_kernel(const uint32_t *__restrict__ ext, const u4 *__restrict__ wf,
                                                      int32_t n, int32_t ntiles, int64_t B,
                                                      const int32_t *__restrict__ io, uint32_t *__restrict__ out)
@@ -72,6 +76,8 @@ __global__ __launch_bounds__(64) void ks_mfma_kernel(const uint32_t *__restrict_
     });
 
     const u4 *wbase = wf + (size_t)(cb * KS_NT) * KT * 64 + lane;   // + ((kappa*ntiles + nt)*KT + kt)*64
+    const int kt0 = SPLIT ? (int)(blockIdx.z * (unsigned)KT / gridDim.z) : 0;
+    const int kt1 = SPLIT ? (int)((blockIdx.z + 1) * (unsigned)KT / gridDim.z) : KT;
 
 #pragma unroll 1
     for (int kappa = 3; kappa >= 0; --kappa) {
@@ -84,11 +90,11 @@ __global__ __launch_bounds__(64) void ks_mfma_kernel(const uint32_t *__restrict_
         // prefetch K-tile 0
         uint32_t xa[KS_MT];
         u4 wb[KS_NT];
-        static_for<0, KS_MT>([&](auto mI) { xa[decltype(mI)::value] = erow[decltype(mI)::value][ihalf]; });
-        static_for<0, KS_NT>([&](auto nI) { wb[decltype(nI)::value] = wk[(size_t)decltype(nI)::value * KT * 64]; });
+        static_for<0, KS_MT>([&](auto mI) { xa[decltype(mI)::value] = erow[decltype(mI)::value][2 * kt0 + ihalf]; });
+        static_for<0, KS_NT>([&](auto nI) { wb[decltype(nI)::value] = wk[((size_t)decltype(nI)::value * KT + kt0) * 64]; });
 #pragma unroll 2
-        for (int kt = 0; kt < KT; ++kt) {
-            const int ktn = kt + 1 < KT ? kt + 1 : kt;
+        for (int kt = kt0; kt < kt1; ++kt) {
+            const int ktn = kt + 1 < kt1 ? kt + 1 : kt;
             uint32_t xn[KS_MT];
             u4 wn[KS_NT];
             static_for<0, KS_MT>([&](auto mI) { xn[decltype(mI)::value] = erow[decltype(mI)::value][2 * ktn + ihalf]; });
@@ -133,15 +139,29 @@ __global__ __launch_bounds__(64) void ks_mfma_kernel(const uint32_t *__restrict_
                 for (int i = 0; i < 4; ++i) {
                     const int64_t g = gbase + 16 * mt + 4 * g4 + i;
                     if (g < B) {
-                        uint32_t v = 0u - (uint32_t)acc[mt][nt][i];
-                        if (col == n) v += ext[g * (N + 1) + N];
+                        const uint32_t v = 0u - (uint32_t)acc[mt][nt][i];
                         const int64_t orow = io ? (int64_t)io[g] : g;
-                        out[orow * (int64_t)(n + 1) + col] = v;
+                        uint32_t *o = out + orow * (int64_t)(n + 1) + col;
+                        if constexpr (SPLIT) atomicAdd(o, v);
+                        else *o = col == n ? v + ext[g * (N + 1) + N] : v;
                     }
                 }
             }
         });
     });
+}
+
+// Output rows of a split-K key switch start as (0, ..., 0, b').
+template <int N>
+__global__ __launch_bounds__(256) void ks_init_kernel(const uint32_t *__restrict__ ext, int32_t n, int64_t B,
+                                                      const int32_t *__restrict__ io, uint32_t *__restrict__ out)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= B * (int64_t)(n + 1)) return;
+    const int64_t g = k / (n + 1);
+    const int col = (int)(k - g * (n + 1));
+    const int64_t orow = io ? (int64_t)io[g] : g;
+    out[orow * (int64_t)(n + 1) + col] = col == n ? ext[g * (N + 1) + N] : 0u;
 }
 
 }  // namespace
@@ -191,10 +211,27 @@ int launch_ks_mfma(const cemu_cloud_key *ck, const uint32_t *ext, const int32_t 
     const int n = ck->p.n, N = ck->p.N;
     const int ntiles = ((n + 1 + 63) / 64) * 4;
     const int64_t gblocks = (B + 16 * KS_MT - 1) / (16 * KS_MT);
-    const dim3 grid((unsigned)gblocks, (unsigned)(ntiles / KS_NT));
+    const int64_t tiles = gblocks * (ntiles / KS_NT);
+    // split the K range when the tiles alone cannot fill the GPU: aim at
+    // about 1024 workgroups, at least 16 K-tiles per split
+    const int KT = N * KS_T * 4 / 64;
+    int splits = 1;
+    while (tiles * splits * 2 <= 1024 && KT / (splits * 2) >= 16) splits *= 2;
+    const dim3 grid((unsigned)gblocks, (unsigned)(ntiles / KS_NT), (unsigned)splits);
     const u4 *wf = reinterpret_cast<const u4 *>(ck->d_ksk_mfma);
-    if (N == 1024) hipLaunchKernelGGL(ks_mfma_kernel<1024>, grid, dim3(64), 0, s, ext, wf, n, ntiles, B, io, out);
-    else hipLaunchKernelGGL(ks_mfma_kernel<512>, grid, dim3(64), 0, s, ext, wf, n, ntiles, B, io, out);
+    if (splits > 1) {
+        const int64_t cells = B * (int64_t)(n + 1);
+        const unsigned ib = (unsigned)((cells + 255) / 256);
+        if (N == 1024) hipLaunchKernelGGL(ks_init_kernel<1024>, dim3(ib), dim3(256), 0, s, ext, n, B, io, out);
+        else hipLaunchKernelGGL(ks_init_kernel<512>, dim3(ib), dim3(256), 0, s, ext, n, B, io, out);
+    }
+    if (N == 1024) {
+        if (splits > 1) hipLaunchKernelGGL((ks_mfma_kernel<1024, true>), grid, dim3(64), 0, s, ext, wf, n, ntiles, B, io, out);
+        else hipLaunchKernelGGL((ks_mfma_kernel<1024, false>), grid, dim3(64), 0, s, ext, wf, n, ntiles, B, io, out);
+    } else {
+        if (splits > 1) hipLaunchKernelGGL((ks_mfma_kernel<512, true>), grid, dim3(64), 0, s, ext, wf, n, ntiles, B, io, out);
+        else hipLaunchKernelGGL((ks_mfma_kernel<512, false>), grid, dim3(64), 0, s, ext, wf, n, ntiles, B, io, out);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("ks_mfma_kernel launch: ") + hipGetErrorString(e));
     return CEMU_OK;
