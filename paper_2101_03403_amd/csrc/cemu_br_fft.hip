@@ -80,41 +80,40 @@ __device__ __forceinline__ d2 cexp_unit(double theta)
 }
 
 // In-register DFT of length 8 over x[0..7]; INV selects the +i sign.
+// Radix-2 split into even and odd outputs; the sqrt(1/2) factors of the odd
+// quarter are applied by the final fused multiply-adds (52 FP64 operations).
 template <bool INV>
 __device__ __forceinline__ void dft8(d2 (&x)[8])
 {
     const double r = 0.70710678118654752440;
-    d2 a0 = x[0] + x[4], a4 = x[0] - x[4];
-    d2 a1 = x[1] + x[5], a5 = x[1] - x[5];
-    d2 a2 = x[2] + x[6], a6 = x[2] - x[6];
-    d2 a3 = x[3] + x[7], a7 = x[3] - x[7];
+    const d2 a0 = x[0] + x[4], a4 = x[0] - x[4];
+    const d2 a1 = x[1] + x[5], a5 = x[1] - x[5];
+    const d2 a2 = x[2] + x[6], a6 = x[2] - x[6];
+    const d2 a3 = x[3] + x[7], a7 = x[3] - x[7];
+    double s1, s2, w1, w2;
+    d2 a6r;
     if constexpr (!INV) {
-        a5 = d2{(a5.x + a5.y) * r, (a5.y - a5.x) * r};    // * (1 - i)/sqrt2
-        a6 = d2{a6.y, -a6.x};                              // * -i
-        a7 = d2{(a7.y - a7.x) * r, -(a7.x + a7.y) * r};   // * (-1 - i)/sqrt2
+        const double u1 = a5.x + a5.y, u2 = a5.y - a5.x, v1 = a7.y - a7.x, v2 = a7.x + a7.y;
+        s1 = u1 + v1; s2 = u2 - v2; w1 = u2 + v2; w2 = v1 - u1;
+        a6r = d2{a6.y, -a6.x};                              // * -i
     } else {
-        a5 = d2{(a5.x - a5.y) * r, (a5.x + a5.y) * r};    // * (1 + i)/sqrt2
-        a6 = d2{-a6.y, a6.x};                              // * i
-        a7 = d2{-(a7.x + a7.y) * r, (a7.x - a7.y) * r};   // * (-1 + i)/sqrt2
+        const double u1 = a5.x - a5.y, u2 = a5.x + a5.y, v1 = a7.x + a7.y, v2 = a7.x - a7.y;
+        s1 = u1 - v1; s2 = u2 + v2; w1 = v2 - u2; w2 = u1 + v1;
+        a6r = d2{-a6.y, a6.x};                              // * i
     }
     const d2 b0 = a0 + a2, b2 = a0 - a2, b1 = a1 + a3;
-    const d2 b4 = a4 + a6, b6 = a4 - a6, b5 = a5 + a7;
-    d2 b3 = a1 - a3, b7 = a5 - a7;
-    if constexpr (!INV) {
-        b3 = d2{b3.y, -b3.x};
-        b7 = d2{b7.y, -b7.x};
-    } else {
-        b3 = d2{-b3.y, b3.x};
-        b7 = d2{-b7.y, b7.x};
-    }
+    const d2 b4 = a4 + a6r, b6 = a4 - a6r;
+    d2 b3 = a1 - a3;
+    if constexpr (!INV) b3 = d2{b3.y, -b3.x};
+    else b3 = d2{-b3.y, b3.x};
     x[0] = b0 + b1;
     x[4] = b0 - b1;
     x[2] = b2 + b3;
     x[6] = b2 - b3;
-    x[1] = b4 + b5;
-    x[5] = b4 - b5;
-    x[3] = b6 + b7;
-    x[7] = b6 - b7;
+    x[1] = d2{fma(r, s1, b4.x), fma(r, s2, b4.y)};
+    x[5] = d2{fma(-r, s1, b4.x), fma(-r, s2, b4.y)};
+    x[3] = d2{fma(r, w1, b6.x), fma(r, w2, b6.y)};
+    x[7] = d2{fma(-r, w1, b6.x), fma(-r, w2, b6.y)};
 }
 
 // x[s] *= b^s for s = 1..7.
