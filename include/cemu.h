@@ -164,6 +164,20 @@ int cemu_blind_rotate_extract(const cemu_cloud_key *ck, int form, const uint8_t 
 int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *out_n, int64_t B,
                     void *hip_stream);
 
+/* Batched homomorphic multiplexer: out_g = s_g ? a_g : b_g (Table
+ * "TFHEbenchmark": MUX, two bootstraps; the FHE MUX select of every stage of
+ * the register-mode barrel shifters, Sec. 5.4). Computed as in TFHE: the
+ * gates AND(s, a) and ANDNY(s, b) are blind-rotated and extracted without key
+ * switching (one batch of 2B blind rotations), their samples are added
+ * together with (0, ..., 0, 1/8), and the sum is key-switched once.
+ *   pool_in:  device uint32_t [P_in][n+1]
+ *   is, ia, ib: device int32_t [B], rows of the selector and of the inputs
+ *             chosen when the selector is true (a) or false (b)
+ *   io, pool_out, stream, alignment, errors: as cemu_bootstrap_gates.
+ * Scratch: the workspaces hold 2B blind-rotation samples. */
+int cemu_mux(const cemu_cloud_key *ck, int form, const uint32_t *pool_in, const int32_t *is, const int32_t *ia,
+             const int32_t *ib, const int32_t *io, uint32_t *pool_out, int64_t B, void *hip_stream);
+
 /* Unbootstrapped operations of Table "TFHEbenchmark" on a device pool
  * [P][n+1]: NOT (negation of every word), COPY, and CONSTANT (trivial
  * ciphertext (0,...,0, +-1/8)). src, dst: device int32_t [count] rows; for

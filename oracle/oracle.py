@@ -286,3 +286,26 @@ def bootstrap_batch(keys: Keys, ops, c1s, c2s, want_extracted: bool = True, want
     if rc != 0:
         raise ValueError("unknown gate op in batch")
     return ext, out
+
+
+# ---------------------------------------------------------------- multiplexer
+OP_AND, OP_ANDNY = 1, 6
+
+
+def mux_batch(keys: Keys, sel, c1s, c2s) -> np.ndarray:
+    """Homomorphic multiplexer out = sel ? c1 : c2 (Table "TFHEbenchmark":
+    MUX, two bootstraps; the FHE MUX select of the barrel shifters, Sec. 5.4),
+    in TFHE's form: AND(sel, c1) and ANDNY(sel, c2) are bootstrapped without
+    key switching; at most one of them is true, so their extracted samples
+    plus the trivial sample (0, ..., 0, 1/8) encrypt +1/8 exactly when the
+    selected input is true and -1/8 otherwise; one key switch follows.
+    Returns [B][n+1]."""
+    sel, c1s, c2s = _u32(sel), _u32(c1s), _u32(c2s)
+    B = sel.shape[0]
+    N = keys.params.N
+    e1, _ = bootstrap_batch(keys, np.full(B, OP_AND, np.int32), sel, c1s, want_out=False)
+    e2, _ = bootstrap_batch(keys, np.full(B, OP_ANDNY, np.int32), sel, c2s, want_out=False)
+    summed = e1 + e2                      # uint32 arithmetic wraps mod 2^32
+    summed[:, N] += np.uint32(1 << 29)
+    return key_switch_batch(keys, summed)
+

@@ -53,7 +53,7 @@ class Params(C.Structure):
 EXPORTED = [
     "cemu_params_default", "cemu_keygen", "cemu_secret_params", "cemu_cloud_params", "cemu_encrypt",
     "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates",
-    "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
+    "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_mux", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
     "cemu_profile_enable", "cemu_profile_read", "cemu_get_tuning", "cemu_set_tuning",
 ]
@@ -83,6 +83,7 @@ def lib() -> C.CDLL:
     L.cemu_bootstrap_gates.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_blind_rotate_extract.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_key_switch.argtypes = [vp, vp, vp, i64, vp]
+    L.cemu_mux.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_lwe_not.argtypes = [i32, vp, vp, vp, vp, i64, vp]
     L.cemu_lwe_copy.argtypes = [i32, vp, vp, vp, vp, i64, vp]
     L.cemu_lwe_constant.argtypes = [i32, vp, vp, vp, i64, vp]
@@ -258,6 +259,13 @@ def blind_rotate_extract(keys: Keys, ops, pool_in, ia, ib, out_N, form="int8", s
 def key_switch(keys: Keys, in_N, out_n, stream=None):
     B = int(in_N.shape[0])
     _check(lib().cemu_key_switch(keys.ck, _dptr(in_N), _dptr(out_n), B, _stream(stream)))
+
+
+def mux(keys: Keys, pool_in, isel, ia, ib, pool_out, io=None, form="int8", stream=None):
+    """Batched homomorphic MUX (isel ? ia : ib); see cemu_mux in include/cemu.h."""
+    B = int(isel.shape[0])
+    _check(lib().cemu_mux(keys.ck, FORMS[form], _dptr(pool_in), _dptr(isel), _dptr(ia), _dptr(ib), _dptr(io),
+                          _dptr(pool_out), B, _stream(stream)))
 
 
 def lwe_not(n: int, pool_in, src, pool_out, dst, stream=None):

@@ -18,6 +18,10 @@ Circuits (built from bootstrapped binary gates plus the free NOT / CONSTANT):
     ``bitwise`` (one gate per bit, Sec. 5.7) and ``array_multiply`` (AND
     partial products accumulated with Kogge-Stone adders) -- the compare,
     bitwise and multiply instructions of the mixed instruction stream.
+  * ``barrel_shift`` -- the register-mode shifters LLS / LRS / ARS of
+    Sec. 5.4: log2 W stages of W FHE MUX selects each (the MUX of Table
+    "TFHEbenchmark", two bootstraps), and ``shift_immediate`` -- the
+    immediate mode, which only moves wires and inserts constants.
 
 Execution: ``Program`` takes any number of circuit instances, assigns each
 bootstrapped gate to a level (one more than its latest bootstrapped input,
@@ -46,7 +50,9 @@ _PLAIN = {
 
 @dataclass
 class Circuit:
-    """A DAG over wires. Kinds: 'in', 'gate' (bootstrapped), 'not', 'const'.
+    """A DAG over wires. Kinds: 'in', 'gate' (bootstrapped), 'mux' (FHE MUX,
+    two bootstraps; node (kind, s, a, b) selects a when s is true), 'not',
+    'const'.
 
     Every wire has a level: 0 for inputs and constants, the input's level for
     NOT, and for a gate the larger of 1 + its inputs' levels and a requested
@@ -73,6 +79,10 @@ class Circuit:
     def gate(self, op: int, a: int, b: int, level: int = 0) -> int:
         return self._new("gate", op, a, b, max(1 + max(self.lv[a], self.lv[b]), level))
 
+    def mux(self, s: int, a: int, b: int, level: int = 0) -> int:
+        """s ? a : b."""
+        return self._new("mux", s, a, b, max(1 + max(self.lv[s], self.lv[a], self.lv[b]), level))
+
     def NOT(self, a: int) -> int:
         return self._new("not", -1, a, -1, self.lv[a])
 
@@ -89,6 +99,8 @@ class Circuit:
                 vals[w] = next(it)
             elif kind == "gate":
                 vals[w] = _PLAIN[op](int(vals[a]), int(vals[b]))
+            elif kind == "mux":
+                vals[w] = vals[a] if vals[op] else vals[b]
             elif kind == "not":
                 vals[w] = 1 - vals[a]
             else:
@@ -99,6 +111,7 @@ class Circuit:
         return np.array(self.lv, dtype=np.int64)
 
     def gate_counts_per_level(self) -> list:
+        """Bootstrapped binary gates per level (MUX nodes not included)."""
         gl = [self.lv[w] for w, n in enumerate(self.nodes) if n[0] == "gate"]
         if not gl:
             return []
@@ -106,10 +119,16 @@ class Circuit:
         return [int(np.sum(gl == L)) for L in range(1, int(gl.max()) + 1)]
 
     def depth(self) -> int:
-        return max([self.lv[w] for w, n in enumerate(self.nodes) if n[0] == "gate"], default=0)
+        return max([self.lv[w] for w, n in enumerate(self.nodes) if n[0] in ("gate", "mux")], default=0)
 
     def num_gates(self) -> int:
         return sum(1 for n in self.nodes if n[0] == "gate")
+
+    def num_muxes(self) -> int:
+        return sum(1 for n in self.nodes if n[0] == "mux")
+
+    def num_bootstraps(self) -> int:
+        return self.num_gates() + 2 * self.num_muxes()
 
 
 # ------------------------------------------------------------------ circuits
@@ -219,6 +238,54 @@ def array_multiply(c: Circuit, A: list, B: list) -> list:
     return out
 
 
+LLS, LRS, ARS = "LLS", "LRS", "ARS"
+
+
+def barrel_shift(c: Circuit, A: list, S: list, mode: str) -> list:
+    """Register-mode shifter (Sec. 5.4, figures LLS / LRS): stage k (k = 0 ..
+    log2 W - 1, in the order of the shift-amount bits) selects for every bit
+    i, with the FHE MUX on amount bit S[k], between the bit 2^k places away
+    and bit i itself. LLS takes bit i - 2^k (zero shifted in); LRS takes bit
+    i + 2^k (zero shifted in); ARS is LRS with the register's sign bit as the
+    shift-in value. W must be a power of two; only the low log2 W amount bits
+    are used, so the amount is taken modulo W."""
+    W = len(A)
+    if W & (W - 1) or W < 2:
+        raise ValueError("barrel_shift needs a power-of-two width")
+    if mode not in (LLS, LRS, ARS):
+        raise ValueError(f"unknown shift mode {mode}")
+    zero = c.const(0)
+    cur = list(A)
+    for k in range(W.bit_length() - 1):
+        d = 1 << k
+        nxt = []
+        for i in range(W):
+            if mode == LLS:
+                src = cur[i - d] if i >= d else zero
+            elif mode == LRS:
+                src = cur[i + d] if i + d < W else zero
+            else:
+                src = cur[i + d] if i + d < W else cur[W - 1]
+            nxt.append(c.mux(S[k], src, cur[i]))
+        cur = nxt
+    return cur
+
+
+def shift_immediate(c: Circuit, A: list, amount: int, mode: str) -> list:
+    """Immediate-mode shift (Sec. 5.4): the amount is cleartext, so the bits
+    are only moved (COPY) and the vacated positions take the constant zero
+    (LLS, LRS) or the sign bit (ARS); nothing is bootstrapped."""
+    W = len(A)
+    k = int(amount) % W
+    if mode == LLS:
+        return [c.const(0) for _ in range(k)] + list(A[:W - k])
+    if mode == LRS:
+        return list(A[k:]) + [c.const(0) for _ in range(k)]
+    if mode == ARS:
+        return list(A[k:]) + [A[W - 1]] * k
+    raise ValueError(f"unknown shift mode {mode}")
+
+
 def adder_instance(width: int, carry_in_one: bool = False):
     """A standalone W-bit ADD (or SUB if carry_in_one and inputs negated by the
     caller) circuit: inputs a[0..W), b[0..W); output 'sum'."""
@@ -255,6 +322,11 @@ class Level:
     ib: np.ndarray
     io: np.ndarray
     nots: tuple         # (src rows, dst rows) executed before the level's gates
+    mux: tuple = (np.zeros(0, np.int32),) * 4   # (selector, a, b, out) rows [M]
+
+    @property
+    def num_muxes(self) -> int:
+        return int(self.mux[0].shape[0])
 
 
 class Program:
@@ -269,6 +341,7 @@ class Program:
         self.offsets = np.cumsum([0] + [len(c.nodes) for c in circuits])
         self.rows = int(self.offsets[-1])
         per_level = {}
+        per_level_mux = {}
         nots = {}
         consts = ([], [])
         for k, c in enumerate(circuits):
@@ -277,19 +350,23 @@ class Program:
                 L = c.lv[w]
                 if kind == "gate":
                     per_level.setdefault(L, []).append((op, off + a, off + b, off + w))
+                elif kind == "mux":
+                    per_level_mux.setdefault(L, []).append((off + op, off + a, off + b, off + w))
                 elif kind == "not":
                     nots.setdefault(L, []).append((off + a, off + w))
                 elif kind == "const":
                     consts[0].append(op)
                     consts[1].append(off + w)
-        depth = max(per_level) if per_level else 0
+        depth = max(list(per_level) + list(per_level_mux), default=0)
         self.levels = []
         for L in range(1, depth + 1):
             arr = np.array(per_level.get(L, []), dtype=np.int64).reshape(-1, 4)
+            mx = np.array(per_level_mux.get(L, []), dtype=np.int64).reshape(-1, 4).astype(np.int32)
             na = np.array(nots.get(L - 1, []), dtype=np.int64).reshape(-1, 2)
             self.levels.append(Level(arr[:, 0].astype(np.uint8), arr[:, 1].astype(np.int32),
                                      arr[:, 2].astype(np.int32), arr[:, 3].astype(np.int32),
-                                     (na[:, 0].astype(np.int32), na[:, 1].astype(np.int32))))
+                                     (na[:, 0].astype(np.int32), na[:, 1].astype(np.int32)),
+                                     (mx[:, 0].copy(), mx[:, 1].copy(), mx[:, 2].copy(), mx[:, 3].copy())))
         # NOTs of the last level's outputs run after the last launch
         tail = np.array(nots.get(depth, []), dtype=np.int64).reshape(-1, 2)
         self.tail_nots = (tail[:, 0].astype(np.int32), tail[:, 1].astype(np.int32))
@@ -304,10 +381,21 @@ class Program:
         return len(self.levels)
 
     def level_widths(self) -> list:
+        """Bootstrapped binary gates per level."""
         return [int(L.ops.shape[0]) for L in self.levels]
+
+    def level_mux_counts(self) -> list:
+        return [L.num_muxes for L in self.levels]
 
     def num_gates(self) -> int:
         return int(sum(self.level_widths()))
+
+    def num_muxes(self) -> int:
+        return int(sum(self.level_mux_counts()))
+
+    def num_bootstraps(self) -> int:
+        """Blind rotations per run: one per gate, two per MUX."""
+        return self.num_gates() + 2 * self.num_muxes()
 
     # ------------------------------------------------------------ device side
     def to_device(self, device):
@@ -318,6 +406,7 @@ class Program:
 
         self._dev = {
             "levels": [(t(L.ops), t(L.ia), t(L.ib), t(L.io), t(L.nots[0]), t(L.nots[1])) for L in self.levels],
+            "mux": [tuple(t(x) for x in L.mux) for L in self.levels],
             "tail": (t(self.tail_nots[0]), t(self.tail_nots[1])),
             "consts": (t(self.consts[0]), t(self.consts[1])),
         }
@@ -325,9 +414,9 @@ class Program:
 
     def run(self, keys, pool, form="fft64", stream=None, profile_levels=None, tuner=None):
         """Enqueue the whole program on `stream`: constants, then per level the
-        NOTs it needs and one batched gate launch (gather/scatter in `pool`).
-        With an autotuner, each level's form and tiles are the tuner's choice
-        for that level's width."""
+        NOTs it needs, one batched gate launch and one batched MUX launch
+        (gather/scatter in `pool`). With an autotuner, each launch's form and
+        tiles are the tuner's choice for its number of blind rotations."""
         import torch
         if self._dev is None:
             self.to_device(pool.device)
@@ -342,8 +431,13 @@ class Program:
             if profile_levels is not None:
                 ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 ev[0].record(stream)
-            f = tuner.apply(int(ops.shape[0])) if tuner is not None else form
-            cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=f, stream=stream)
+            if ops.shape[0]:
+                f = tuner.apply(int(ops.shape[0])) if tuner is not None else form
+                cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=f, stream=stream)
+            ms, ma, mb, mo = d["mux"][li]
+            if ms.shape[0]:
+                f = tuner.apply(2 * int(ms.shape[0])) if tuner is not None else form
+                cemu.mux(keys, pool, ms, ma, mb, pool, io=mo, form=f, stream=stream)
             if ev is not None:
                 ev[1].record(stream)
                 profile_levels.append(ev)
@@ -367,8 +461,9 @@ class Program:
 
 
 def instruction_circuit(kind: str, width: int) -> Circuit:
-    """One instruction of the mixed stream as a circuit with inputs a, b
-    (width bits each, LSB first) and output 'out'."""
+    """One instruction as a circuit with inputs a, b (width bits each, LSB
+    first) and output 'out'. Shifts (LLS / LRS / ARS) are register mode: b is
+    the shift-amount register."""
     c = Circuit()
     A = c.inputs_word(width)
     B = c.inputs_word(width)
@@ -384,6 +479,8 @@ def instruction_circuit(kind: str, width: int) -> Circuit:
         out = [equal(c, A, B)]
     elif kind in ("AND", "OR", "XOR"):
         out = bitwise(c, {"AND": AND, "OR": OR, "XOR": XOR}[kind], A, B)
+    elif kind in (LLS, LRS, ARS):
+        out = barrel_shift(c, A, B, kind)
     else:
         raise ValueError(f"unknown instruction {kind}")
     c.outputs["out"] = out
@@ -393,5 +490,13 @@ def instruction_circuit(kind: str, width: int) -> Circuit:
 def instruction_result(kind: str, width: int, a: int, b: int) -> int:
     """Cleartext result the circuit must decrypt to."""
     m = (1 << width) - 1
+    if kind in (LLS, LRS, ARS):
+        k = b % width
+        if kind == LLS:
+            return (a << k) & m
+        if kind == LRS:
+            return a >> k
+        signed = a - (1 << width) if a >> (width - 1) else a
+        return (signed >> k) & m
     return {"ADD": (a + b) & m, "SUB": (a - b) & m, "MUL": a * b, "LT": int(a < b), "EQ": int(a == b),
             "AND": a & b, "OR": a | b, "XOR": a ^ b}[kind]

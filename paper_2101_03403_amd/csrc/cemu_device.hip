@@ -58,6 +58,41 @@ __global__ void lincomb_modswitch_kernel(const uint8_t *__restrict__ ops, const 
     bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
 }
 
+// Multiplexer, first half: the two gates AND(s, a) and ANDNY(s, b) of every
+// MUX g as one batch of 2B gates (g and B + g), lincomb and modulus switch
+// exactly as lincomb_modswitch_kernel.
+__global__ void mux_lincomb_kernel(const uint32_t *__restrict__ pool, const int32_t *__restrict__ is,
+                                   const int32_t *__restrict__ ia, const int32_t *__restrict__ ib, int32_t n,
+                                   int32_t log2_2n, int64_t B, uint16_t *__restrict__ bars)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = n + 1;
+    if (idx >= 2 * B * row) return;
+    const int64_t g2 = idx / row;
+    const int32_t u = (int32_t)(idx - g2 * row);
+    const bool second = g2 >= B;
+    const int64_t g = second ? g2 - B : g2;
+    const int op = second ? CEMU_ANDNY : CEMU_AND;
+    const uint32_t x1 = pool[(int64_t)is[g] * row + u];
+    const uint32_t x2 = pool[(int64_t)(second ? ib[g] : ia[g]) * row + u];
+    uint32_t x = (uint32_t)c_gate_w1[op] * x1 + (uint32_t)c_gate_w2[op] * x2;
+    if (u == n) x += c_gate_kappa[op];
+    const uint32_t half = 1u << (31 - log2_2n);
+    bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
+}
+
+// Multiplexer, second half: ext[g] += ext[B + g] + (0, ..., 0, 1/8). Both
+// extracted samples encrypt -1/8 except the one of the selected input when
+// it is true, so the sum encrypts +-1/8 for the selected bit.
+__global__ void mux_combine_kernel(uint32_t *__restrict__ ext, int32_t N, int64_t B)
+{
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t row = N + 1;
+    if (idx >= B * row) return;
+    const int64_t j = idx - (idx / row) * row;
+    ext[idx] += ext[idx + B * row] + (j == N ? 0x20000000u : 0u);
+}
+
 // K3: key switching N -> n. A workgroup takes KS_G samples; thread t owns
 // output columns t, t+256, t+512 for all of them. The rounded inputs are
 // staged in LDS; each key row is read once per workgroup and applied to the
@@ -259,12 +294,10 @@ int check_device(const cemu_cloud_key *ck)
     return CEMU_OK;
 }
 
-// Lincomb + blind rotation + extraction into ext_out ([B][N+1]).
-int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
-                     const int32_t *ib, uint32_t *ext_out, int64_t B, hipStream_t s)
+// Blind rotation + extraction of the B gates whose bars are in the workspace.
+int run_br(cemu_cloud_key *ck, int form, uint32_t *ext_out, int64_t B, hipStream_t s)
 {
-    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, s);
-    if (rc) return rc;
+    int rc;
     void *ev = prof_begin(ck, s);
     if (form == CEMU_FORM_INT8) rc = launch_br_int8(ck, ck->d_bars, B, ext_out, s);
     else if (form == CEMU_FORM_FFT64) rc = launch_br_fft(ck, ck->d_bars, B, ext_out, s);
@@ -272,6 +305,38 @@ int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uin
     if (rc == CEMU_OK) prof_end(ck, form == CEMU_FORM_INT8 ? 1 : 2, s, ev);
     else if (ev) (void)hipEventDestroy((hipEvent_t)ev);
     return rc;
+}
+
+// Lincomb + blind rotation + extraction into ext_out ([B][N+1]).
+int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
+                     const int32_t *ib, uint32_t *ext_out, int64_t B, hipStream_t s)
+{
+    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, s);
+    if (rc) return rc;
+    return run_br(ck, form, ext_out, B, s);
+}
+
+int run_mux(cemu_cloud_key *ck, int form, const uint32_t *pool, const int32_t *is, const int32_t *ia,
+            const int32_t *ib, const int32_t *io, uint32_t *pool_out, int64_t B, hipStream_t s)
+{
+    const int32_t n = ck->p.n, N = ck->p.N;
+    const int threads = 256;
+    {
+        const int64_t blocks = (2 * B * (n + 1) + threads - 1) / threads;
+        void *ev = prof_begin(ck, s);
+        hipLaunchKernelGGL(mux_lincomb_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, pool, is, ia, ib, n,
+                           log2_of(2 * N), B, ck->d_bars);
+        CEMU_HIP(hipGetLastError());
+        prof_end(ck, 0, s, ev);
+    }
+    int rc = run_br(ck, form, ck->d_ext, 2 * B, s);
+    if (rc) return rc;
+    {
+        const int64_t blocks = (B * (N + 1) + threads - 1) / threads;
+        hipLaunchKernelGGL(mux_combine_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, ck->d_ext, N, B);
+        CEMU_HIP(hipGetLastError());
+    }
+    return launch_key_switch(ck, ck->d_ext, io, pool_out, B, s);
 }
 
 }  // namespace
@@ -385,6 +450,28 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ckc, int form, const uint8_t *ops
     rc = run_blind_rotate(ck, form, ops, pool_in, ia, ib, ck->d_ext, B, s);
     if (rc) return rc;
     return launch_key_switch(ck, ck->d_ext, io, pool_out, B, s);
+}
+
+int cemu_mux(const cemu_cloud_key *ckc, int form, const uint32_t *pool_in, const int32_t *is, const int32_t *ia,
+             const int32_t *ib, const int32_t *io, uint32_t *pool_out, int64_t B, void *hip_stream)
+{
+    clear_error();
+    if (!ckc) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
+    if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
+    if (B == 0) return CEMU_OK;
+    if (B > ((int64_t)1 << 40)) return fail(CEMU_ERR_RANGE, "batch too large");
+    if (!pool_in || !is || !ia || !ib || !pool_out) return fail(CEMU_ERR_NULL, "NULL device buffer");
+    if (misaligned(pool_in) || misaligned(is) || misaligned(ia) || misaligned(ib) || misaligned(pool_out) ||
+        (io && misaligned(io)))
+        return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    cemu_cloud_key *ck = const_cast<cemu_cloud_key *>(ckc);
+    std::lock_guard<std::mutex> lock(ck->mu);
+    int rc = check_device(ck);
+    if (rc) return rc;
+    rc = ensure_workspace(ck, 2 * B, true);
+    if (rc) return rc;
+    return run_mux(ck, form, pool_in, is, ia, ib, io, pool_out, B, (hipStream_t)hip_stream);
 }
 
 int cemu_blind_rotate_extract(const cemu_cloud_key *ckc, int form, const uint8_t *ops, const uint32_t *pool_in,

@@ -95,8 +95,12 @@ def _run_with_oracle(prog, okeys, in_bits, enc_seed=3):
     for L in prog.levels:
         src, dst = L.nots
         pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
-        _, out = O.bootstrap_batch(okeys, L.ops.astype(np.int32), pool[L.ia], pool[L.ib], want_extracted=False)
-        pool[L.io] = out
+        if L.ops.shape[0]:
+            _, out = O.bootstrap_batch(okeys, L.ops.astype(np.int32), pool[L.ia], pool[L.ib], want_extracted=False)
+            pool[L.io] = out
+        if L.num_muxes:
+            ms, ma, mb, mo = L.mux
+            pool[mo] = O.mux_batch(okeys, pool[ms], pool[ma], pool[mb])
     src, dst = prog.tail_nots
     pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
     return pool
@@ -118,3 +122,62 @@ def test_small_circuits_under_fhe_with_oracle():
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
         assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+
+
+# ------------------------------------------------------------------ shifters (Sec. 5.4)
+@pytest.mark.parametrize("mode", [C.LLS, C.LRS, C.ARS])
+@pytest.mark.parametrize("width", [8, 16, 32])
+def test_barrel_shift_cleartext(mode, width):
+    rng = np.random.default_rng(width + len(mode))
+    c = C.instruction_circuit(mode, width)
+    amounts = list(range(width + 3)) + [int(x) for x in rng.integers(0, 1 << width, 8, dtype=np.uint64)]
+    for k in amounts:
+        a = int(rng.integers(0, 1 << width, dtype=np.uint64))
+        if k % 3 == 0:
+            a |= 1 << (width - 1)                     # exercise the sign fill of ARS
+        v = c.eval_plain(C.int_to_bits(a, width) + C.int_to_bits(k, width))
+        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(mode, width, a, k), (a, k)
+
+
+def test_barrel_shift_structure_32():
+    """32-bit register-mode shifter: 5 stages of 32 MUX selects (the thread
+    counts of the 32-bit LLS / LRS / ARS tables), 320 bootstraps."""
+    for mode in (C.LLS, C.LRS, C.ARS):
+        c = C.instruction_circuit(mode, 32)
+        prog = C.Program([c])
+        assert prog.depth == 5
+        assert prog.level_mux_counts() == [32] * 5
+        assert prog.level_widths() == [0] * 5
+        assert prog.num_bootstraps() == 320 == c.num_bootstraps()
+
+
+@pytest.mark.parametrize("mode", [C.LLS, C.LRS, C.ARS])
+def test_shift_immediate_cleartext(mode):
+    rng = np.random.default_rng(7)
+    for k in range(0, 20):
+        c = C.Circuit()
+        A = c.inputs_word(16)
+        out = C.shift_immediate(c, A, k, mode)
+        assert c.num_bootstraps() == 0
+        a = int(rng.integers(0, 1 << 16)) | (1 << 15) * (k % 2)
+        v = c.eval_plain(C.int_to_bits(a, 16))
+        assert C.bits_to_int(v[out]) == C.instruction_result(mode, 16, a, k)
+
+
+def test_shifters_under_fhe_with_oracle():
+    """8-bit LLS and 4-bit LRS / ARS, register mode, evaluated with the
+    oracle's MUX (toy parameters), then decrypted."""
+    from oracle import oracle as O
+    okeys = O.keygen(O.TOY, 98)
+    cases = [(C.LLS, 8, 0b10110101, 3), (C.LRS, 4, 0b1101, 1), (C.ARS, 4, 0b1010, 2)]
+    cs = [C.instruction_circuit(k, w) for k, w, _, _ in cases]
+    prog = C.Program(cs)
+    bits = []
+    for k, w, a, b in cases:
+        bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
+    pool = _run_with_oracle(prog, okeys, bits, enc_seed=8)
+    for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
+        rows = np.array(c.outputs["out"]) + off
+        got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
+        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+

@@ -259,6 +259,23 @@ def test_gate_truth_tables_toy(toy_keys):
     assert np.abs(e).max() < (1 << 26)
 
 
+def test_mux_truth_table_toy(toy_keys):
+    """MUX(s, a, b) = s ? a : b for all eight input rows, under decryption,
+    with the output phase near +-1/8."""
+    k = toy_keys
+    rows = np.array(list(itertools.product([0, 1], repeat=3)) * 3, np.uint8)
+    s, a, b = rows[:, 0], rows[:, 1], rows[:, 2]
+    cs = O.encrypt_bits(k, s, seed=31)
+    ca = O.encrypt_bits(k, a, seed=32)
+    cb = O.encrypt_bits(k, b, seed=33)
+    out = O.mux_batch(k, cs, ca, cb)
+    want = np.where(s == 1, a, b).astype(np.uint8)
+    assert np.array_equal(O.decrypt_bits(k.lwe_key, out), want)
+    ph = np.array([O.lwe_phase(k.lwe_key, c) for c in out], dtype=np.uint32)
+    mu = np.where(want == 1, 1 << 29, M32 - (1 << 29))
+    assert np.abs(to_i32((ph.astype(np.int64) - mu) % M32)).max() < (1 << 26)
+
+
 # ------------------------------------------------------------------ noiseless exactness
 FULL = O.Params(n=64, N=256, l=4, bgbit=8, t=16, basebit=2, sigma_lwe=0.0, sigma_ks=0.0, sigma_bk=0.0)
 
@@ -405,3 +422,17 @@ def test_key_switch_noise_variance(toy_keys):
     # and the key-averaged closed form is within its own spread
     avg = p.N * p.t * 0.75 * (p.sigma_ks * 2.0 ** 32) ** 2
     assert (row_noise[..., 1:] ** 2).mean() * 0.75 * p.N * p.t == pytest.approx(avg, rel=0.05)
+
+
+def test_mux_exact_without_noise(full_keys):
+    """Noiseless, full precision: the multiplexer's output phase is exactly
+    +1/8 for a selected true input and -1/8 otherwise (pins the two gate
+    choices and the added 1/8)."""
+    k = full_keys
+    rows = np.array(list(itertools.product([0, 1], repeat=3)), np.uint8)
+    s, a, b = rows[:, 0], rows[:, 1], rows[:, 2]
+    out = O.mux_batch(k, O.encrypt_bits(k, s, seed=3), O.encrypt_bits(k, a, seed=4), O.encrypt_bits(k, b, seed=5))
+    for g in range(8):
+        mu = (1 << 29) if (a[g] if s[g] else b[g]) else M32 - (1 << 29)
+        assert O.lwe_phase(k.lwe_key, out[g]) == mu
+
