@@ -43,8 +43,8 @@ FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
 # plain 1 GiB copy); summary and commands in profiles/. Valid only while the
 # kernel source is the one profiled (sha256 prefix), else reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "d095ed9b85788bcc",
-              "bytes": 488_564 * 1024 * 2 + 19_472 * 1024, "batch": 4096},
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "99c9480f5662fd75",
+              "bytes": 487_047 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
     "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "65afeedf9381a23e",
              "bytes": 245_914 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
 }
@@ -68,10 +68,13 @@ def parse():
     ap.add_argument("--form", default="fft64", choices=["int8", "fft64"],
                     help="form whose throughput is the reported value (the other is timed too)")
     ap.add_argument("--only", action="store_true", help="time only --form")
+    ap.add_argument("--fft-gates-per-wg", type=int, default=8, choices=[1, 4, 8],
+                    help="FFT64 launch shape of the throughput loop (1 = the one-gate-per-workgroup latency kernel)")
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
     ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
+    ap.add_argument("--no-shift", action="store_true", help="skip the 32-bit barrel-shifter latency measurement")
     ap.add_argument("--add-instances", type=int, default=256)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed instruction stream")
     ap.add_argument("--no-autotune", action="store_true", help="circuits use --form with default tiles")
@@ -170,6 +173,46 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None):
     return out
 
 
+def shift32_latency(keys, dev, form, reps=3, tuner=None):
+    """32-bit register-mode barrel shifters LLS / LRS / ARS (Sec. 5.4): one
+    instance each, 5 levels of 32 FHE MUX selects, captured as a hipGraph;
+    latency = median replay. The paper reports 474.7 / 472.9 / 491.8 ms on
+    its 48-core node."""
+    import torch
+    from paper_2101_03403_amd import circuits as Cc, workloads as W
+
+    out = {}
+    for mode in (Cc.LLS, Cc.LRS, Cc.ARS):
+        rng = np.random.default_rng({"LLS": 11, "LRS": 12, "ARS": 13}[mode])
+        a = int(rng.integers(0, 1 << 32, dtype=np.uint64)) | (1 << 31)
+        amt = int(rng.integers(1, 32))
+        c = Cc.instruction_circuit(mode, 32)
+        prog = Cc.Program([c]).to_device(dev)
+        pool = torch.zeros((prog.rows, keys.n + 1), dtype=torch.int32, device=dev)
+        enc = keys.encrypt(np.asarray(Cc.int_to_bits(a, 32) + Cc.int_to_bits(amt, 32), np.uint8), seed=W.ENC_SEED + 9)
+        pool[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = torch.from_numpy(enc.view(np.int32)).to(dev)
+        prog.run(keys, pool, form=form, tuner=tuner)
+        torch.cuda.synchronize()
+        g = prog.capture(keys, pool, form=form, tuner=tuner)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        host = pool.cpu().numpy().view(np.uint32)
+        got = Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"])]))
+        out[mode] = {"latency_ms": float(np.median(times)), "muxes": prog.num_muxes(),
+                     "bootstraps": prog.num_bootstraps(), "levels": prog.depth,
+                     "decrypt_exact": int(got == Cc.instruction_result(mode, 32, a, amt))}
+    out["form"] = form if tuner is None else "autotuned per launch width"
+    out["timing"] = "hipGraph of the 5 MUX levels, median of 3 replays (hip events)"
+    return out
+
+
 def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
     """1024 independent instructions (40 % ADD/SUB, 20 % 8x8/16x16 array MUL,
     20 % LT/EQ, 20 % AND/OR/XOR; widths 8/16/32), gates of each level merged
@@ -207,7 +250,10 @@ def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
             "level_width_histogram": hist, "form": form if tuner is None else "autotuned per level width"}
 
 
-def roofline(form, prof, B):
+FFT_KERNEL = {8: "br_fft_kernel<8>", 4: "br_fft_kernel<4>", 1: "br_fft_lat_kernel"}
+
+
+def roofline(form, prof, B, fft_gates_per_wg=8):
     if form == "int8":
         ms, cnt = prof["blind_rotate_int8"]
         avg = ms / max(cnt, 1)
@@ -220,7 +266,8 @@ def roofline(form, prof, B):
     avg = ms / max(cnt, 1)
     ach = FFT_FLOP_PER_GATE * B / (avg * 1e-3)
     return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
-            "frac": ach / PEAK_FP64_FLOPS, "traffic": traffic_bytes("fft64", B), "kernel": "br_fft_kernel",
+            "frac": ach / PEAK_FP64_FLOPS, "traffic": traffic_bytes("fft64", B) if fft_gates_per_wg == 8 else None,
+            "kernel": FFT_KERNEL[fft_gates_per_wg],
             "avg_ms": avg, "algorithmic_per_launch": FFT_FLOP_PER_GATE * B,
             "algorithmic_per_gate": "n*(8*(5*512*9 + 6*512) + 12*512*8) = 1.63e8 FP64 flop"}
 
@@ -246,6 +293,7 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
         return
     keys = cemu.keygen(cemu.STD, W.KEY_SEED)
+    cemu.set_tuning(keys, fft_gates_per_wg=args.fft_gates_per_wg)
     B = args.batch
     ops, a, b = W.gate_batch(B, seed=1)
     c1 = keys.encrypt(a, seed=W.ENC_SEED)
@@ -268,7 +316,7 @@ def main():
         outs[form] = host
         res[form] = {
             "value": B / (wall / args.steps), "ms_per_step": wall * 1e3 / args.steps,
-            "roofline": roofline(form, prof, B),
+            "roofline": roofline(form, prof, B, args.fft_gates_per_wg),
             "kernels": {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()},
             "decrypt_exact": f"{int(np.sum(keys.decrypt(host) == want))}/{B}",
         }
@@ -278,11 +326,12 @@ def main():
         primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
 
     tuner = None
-    if not args.no_autotune and not (args.no_add and args.no_mixed):
+    if not args.no_autotune and not (args.no_add and args.no_mixed and args.no_shift):
         from paper_2101_03403_amd.autotune import Autotuner
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
+    rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -305,6 +354,8 @@ def main():
         rec["add32"] = rec_add
     if rec_mix is not None:
         rec["mixed_stream"] = rec_mix
+    if rec_shift is not None:
+        rec["shift32"] = rec_shift
     if tuner is not None:
         rec["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner.measurements.get(b)}
                            for b, c in sorted(tuner.table.items())}
