@@ -18,6 +18,10 @@ Circuits (built from bootstrapped binary gates plus the free NOT / CONSTANT):
     ``bitwise`` (one gate per bit, Sec. 5.7) and ``array_multiply`` (AND
     partial products accumulated with Kogge-Stone adders) -- the compare,
     bitwise and multiply instructions of the mixed instruction stream.
+  * ``sequential_multiply`` (unsigned and signed) and ``nonrestoring_divide``
+    -- the paper's multiplier (Sec. 5.5: W iterations of an AND row and a
+    W-bit adder) and divider (Sec. 5.6: W iterations of an add/subtract
+    adder), long chains of narrow levels.
   * ``barrel_shift`` -- the register-mode shifters LLS / LRS / ARS of
     Sec. 5.4: log2 W stages of W FHE MUX selects each (the MUX of Table
     "TFHEbenchmark", two bootstraps), and ``shift_immediate`` -- the
@@ -164,6 +168,34 @@ def kogge_stone_add(c: Circuit, A: list, B: list, carry_in: int | None = None):
     return s, G[W - 1]
 
 
+def add_with_carry_wire(c: Circuit, A: list, B: list, cin: int):
+    """Kogge-Stone A + B + cin with an encrypted carry-in wire: the carry is
+    prefix position -1 with (G, P) = (cin, 0), so it enters through the same
+    o levels as every other position (ceil(log2(W + 1)) prefix levels).
+    Returns (sum wires, carry-out wire)."""
+    W = len(A)
+    base = max(c.lv[w] for w in list(A) + list(B) + [cin])
+    g = [c.gate(AND, A[i], B[i], base + 1) for i in range(W)]
+    p = [c.gate(XOR, A[i], B[i], base + 1) for i in range(W)]
+    G = [cin] + g                  # index 0 = position -1
+    P = [None] + list(p)           # None = known zero
+    d, k = 1, 1
+    while d < W + 1:
+        newG, newP = {}, {}
+        for i in range(d, W + 1):
+            tmp = c.gate(AND, P[i], G[i - d], base + 2 * k)
+            newP[i] = None if P[i - d] is None else c.gate(AND, P[i], P[i - d], base + 2 * k)
+            newG[i] = c.gate(OR, G[i], tmp, base + 2 * k + 1)
+        for i in newG:
+            G[i] = newG[i]
+            P[i] = newP[i]
+        d *= 2
+        k += 1
+    last = base + 2 * k
+    s = [c.gate(XOR, p[i], G[i], last) for i in range(W)]   # G[i] = carry into bit i
+    return s, G[W]
+
+
 def subtract(c: Circuit, A: list, B: list):
     """a - b = a + NOT(b) + 1 (Sec. 5.3). Returns (difference wires, carry-out
     wire; carry-out 1 means no borrow, i.e. a >= b unsigned)."""
@@ -284,6 +316,59 @@ def shift_immediate(c: Circuit, A: list, amount: int, mode: str) -> list:
     if mode == ARS:
         return list(A[k:]) + [A[W - 1]] * k
     raise ValueError(f"unknown shift mode {mode}")
+
+
+def sequential_multiply(c: Circuit, A: list, B: list, signed: bool = False) -> list:
+    """The paper's sequential (carry-save) multiplier (Sec. 5.5): P = 0; W
+    times: (P, carry) = P + (B[i] ? A : 0) with a W-bit Kogge-Stone adder,
+    then [carry, P, B] >> 1, so bit i of the product is the low sum bit of
+    iteration i and the high word is the final P (2W-bit result). The row
+    bits are ANDs of A with one bit of B; they depend only on the inputs, so
+    they all land in the first level and each iteration is one adder deep.
+
+    signed: two's-complement operands, sign extension removed by the usual
+    constant ("magic number") correction. Row i < W-1 has its MSB inverted
+    (NAND instead of AND), the last row (weight -2^(W-1)) has its other bits
+    inverted, and the constant 2^(2W-1) + 2^W this leaves is added as P's
+    initial value 2^(W-1), a carry-in of 1 on the last iteration (the other
+    2^(W-1)), and an unbootstrapped NOT of the product's MSB."""
+    W = len(A)
+    P = [c.const(0) for _ in range(W - 1)] + [c.const(1 if signed else 0)]
+    low = []
+    for i in range(W):
+        last = i == W - 1
+        row = []
+        for j in range(W):
+            invert = signed and ((j == W - 1) != last)
+            row.append(c.gate(NAND if invert else AND, A[j], B[i]))
+        S, carry = kogge_stone_add(c, P, row, carry_in=1 if (signed and last) else None)
+        low.append(S[0])
+        P = S[1:] + [carry]
+    out = low + P
+    if signed:
+        out[2 * W - 1] = c.NOT(out[2 * W - 1])
+    return out
+
+
+def nonrestoring_divide(c: Circuit, Q: list, D: list) -> list:
+    """Unsigned non-restoring division (Sec. 5.6): A = 0 (one bit wider than
+    the operands, the sign bit), W times: shift [A, Q] left, then A = A - D
+    if A was >= 0 before the shift, else A = A + D, and Q[0] = NOT sign(A).
+    The add/subtract is one adder whose second operand is D XOR SUB with
+    carry-in SUB = NOT sign(A) (the paper's adder with SUB select). The
+    remainder is not corrected (the instruction only returns the quotient);
+    division by zero returns 2^W - 1."""
+    W = len(Q)
+    A = [c.const(0) for _ in range(W + 1)]
+    Q = list(Q)
+    for _ in range(W):
+        sub = c.NOT(A[W])
+        A = [Q[W - 1]] + A[:W]
+        Q = [None] + Q[:W - 1]
+        Dx = [c.gate(XOR, D[j], sub) for j in range(W)] + [sub]   # D's top bit is 0
+        A, _ = add_with_carry_wire(c, A, Dx, sub)
+        Q[0] = c.NOT(A[W])
+    return Q
 
 
 def adder_instance(width: int, carry_in_one: bool = False):
@@ -481,6 +566,12 @@ def instruction_circuit(kind: str, width: int) -> Circuit:
         out = bitwise(c, {"AND": AND, "OR": OR, "XOR": XOR}[kind], A, B)
     elif kind in (LLS, LRS, ARS):
         out = barrel_shift(c, A, B, kind)
+    elif kind == "MULSEQ":
+        out = sequential_multiply(c, A, B, signed=False)
+    elif kind == "SMULSEQ":
+        out = sequential_multiply(c, A, B, signed=True)
+    elif kind == "DIV":
+        out = nonrestoring_divide(c, A, B)
     else:
         raise ValueError(f"unknown instruction {kind}")
     c.outputs["out"] = out
@@ -498,5 +589,11 @@ def instruction_result(kind: str, width: int, a: int, b: int) -> int:
             return a >> k
         signed = a - (1 << width) if a >> (width - 1) else a
         return (signed >> k) & m
-    return {"ADD": (a + b) & m, "SUB": (a - b) & m, "MUL": a * b, "LT": int(a < b), "EQ": int(a == b),
-            "AND": a & b, "OR": a | b, "XOR": a ^ b}[kind]
+    if kind == "SMULSEQ":
+        sa = a - (1 << width) if a >> (width - 1) else a
+        sb = b - (1 << width) if b >> (width - 1) else b
+        return (sa * sb) % (1 << (2 * width))
+    if kind == "DIV":
+        return a // b if b else m
+    return {"ADD": (a + b) & m, "SUB": (a - b) & m, "MUL": a * b, "MULSEQ": a * b, "LT": int(a < b),
+            "EQ": int(a == b), "AND": a & b, "OR": a | b, "XOR": a ^ b}[kind]

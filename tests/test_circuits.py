@@ -181,3 +181,75 @@ def test_shifters_under_fhe_with_oracle():
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
         assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
 
+
+# ------------------------------------------------------------------ multiplier and divider (Sec. 5.5, 5.6)
+SEQ_KINDS = ["MULSEQ", "SMULSEQ", "DIV"]
+
+
+@pytest.mark.parametrize("kind", SEQ_KINDS)
+def test_sequential_units_exhaustive_4bit(kind):
+    c = C.instruction_circuit(kind, 4)
+    for a in range(16):
+        for b in range(16):
+            v = c.eval_plain(C.int_to_bits(a, 4) + C.int_to_bits(b, 4))
+            assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, 4, a, b), (a, b)
+
+
+@pytest.mark.parametrize("kind", SEQ_KINDS)
+@pytest.mark.parametrize("width", [8, 16, 32])
+def test_sequential_units_cleartext(kind, width):
+    rng = np.random.default_rng(width * 7 + len(kind))
+    c = C.instruction_circuit(kind, width)
+    m = (1 << width) - 1
+    cases = [(m, m), (0, 5), (m, 1), (1 << (width - 1), m), (5, 0)]
+    cases += [tuple(int(x) for x in rng.integers(0, 1 << width, 2, dtype=np.uint64)) for _ in range(25)]
+    cases += [(int(rng.integers(0, 1 << width, dtype=np.uint64)), int(rng.integers(1, 1 << (width // 2)))) for _ in range(10)]
+    for a, b in cases:
+        v = c.eval_plain(C.int_to_bits(a, width) + C.int_to_bits(b, width))
+        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, width, a, b), (a, b)
+
+
+def test_sequential_units_structure():
+    """W iterations of one W-bit adder (multiplier) or one (W+1)-bit
+    add/subtract (divider): the depth grows linearly in W, the widest level is
+    the first (all W^2 row ANDs) for the multiplier and one adder stage for the
+    divider."""
+    for w, mul_depth, div_depth in [(8, 65, 88), (16, 161, 208), (32, 385, 480)]:
+        m = C.instruction_circuit("MULSEQ", w)
+        d = C.instruction_circuit("DIV", w)
+        assert m.depth() == mul_depth and d.depth() == div_depth
+        pm = C.Program([m])
+        assert pm.level_widths()[0] == w * w
+        assert max(C.Program([d]).level_widths()) <= 2 * w + 2
+
+
+def test_add_with_carry_wire_cleartext():
+    for w in (1, 3, 8, 17):
+        c = C.Circuit()
+        A, B = c.inputs_word(w), c.inputs_word(w)
+        cin = c.input()
+        s, cout = C.add_with_carry_wire(c, A, B, cin)
+        rng = np.random.default_rng(w)
+        for _ in range(40):
+            a, b, ci = int(rng.integers(0, 1 << w)), int(rng.integers(0, 1 << w)), int(rng.integers(0, 2))
+            v = c.eval_plain(C.int_to_bits(a, w) + C.int_to_bits(b, w) + [ci])
+            assert C.bits_to_int(v[s]) + (int(v[cout]) << w) == a + b + ci
+
+
+def test_sequential_units_under_fhe_with_oracle():
+    """4-bit unsigned and signed sequential multiplication and 4-bit division,
+    evaluated homomorphically with the oracle (toy parameters), decrypted."""
+    from oracle import oracle as O
+    okeys = O.keygen(O.TOY, 97)
+    cases = [("MULSEQ", 4, 13, 11), ("SMULSEQ", 4, 0b1101, 0b0110), ("DIV", 4, 14, 3)]
+    cs = [C.instruction_circuit(k, w) for k, w, _, _ in cases]
+    prog = C.Program(cs)
+    bits = []
+    for k, w, a, b in cases:
+        bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
+    pool = _run_with_oracle(prog, okeys, bits, enc_seed=9)
+    for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
+        rows = np.array(c.outputs["out"]) + off
+        got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
+        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+
