@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
     ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
     ap.add_argument("--no-shift", action="store_true", help="skip the 32-bit barrel-shifter latency measurement")
+    ap.add_argument("--no-seq", action="store_true",
+                    help="skip the 32-bit sequential multiplier / divider latency measurement")
     ap.add_argument("--add-instances", type=int, default=256)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed instruction stream")
     ap.add_argument("--no-autotune", action="store_true", help="circuits use --form with default tiles")
@@ -213,6 +215,51 @@ def shift32_latency(keys, dev, form, reps=3, tuner=None):
     return out
 
 
+def sequential_units(keys, dev, form, width=32, reps=2, tuner=None):
+    """The paper's sequential multiplier (unsigned and signed) and the
+    non-restoring divider (Sec. 5.5, 5.6), one instance each: W iterations
+    of a W- or (W+1)-bit adder, hundreds of narrow levels, captured as a
+    hipGraph; latency = median replay. The paper reports, for 32 bits on its
+    48-core node, 36,929 ms (unsigned), 34,826 ms (signed) and 38,257 ms
+    (divider); for 16 bits 11,317 / 13,121 / 11,660 ms."""
+    import torch
+    from paper_2101_03403_amd import circuits as Cc, workloads as W
+
+    out = {}
+    for kind in ("MULSEQ", "SMULSEQ", "DIV"):
+        rng = np.random.default_rng({"MULSEQ": 21, "SMULSEQ": 22, "DIV": 23}[kind])
+        a = int(rng.integers(0, 1 << width, dtype=np.uint64))
+        b = int(rng.integers(1, 1 << width, dtype=np.uint64))
+        if kind == "DIV":
+            b = int(rng.integers(1, 1 << (width // 2)))
+        c = Cc.instruction_circuit(kind, width)
+        prog = Cc.Program([c]).to_device(dev)
+        pool = torch.zeros((prog.rows, keys.n + 1), dtype=torch.int32, device=dev)
+        enc = keys.encrypt(np.asarray(Cc.int_to_bits(a, width) + Cc.int_to_bits(b, width), np.uint8),
+                           seed=W.ENC_SEED + 10)
+        pool[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = torch.from_numpy(enc.view(np.int32)).to(dev)
+        prog.run(keys, pool, form=form, tuner=tuner)
+        torch.cuda.synchronize()
+        g = prog.capture(keys, pool, form=form, tuner=tuner)
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        host = pool.cpu().numpy().view(np.uint32)
+        got = Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"])]))
+        out[kind] = {"latency_ms": float(np.median(times)), "gates": prog.num_gates(), "levels": prog.depth,
+                     "decrypt_exact": int(got == Cc.instruction_result(kind, width, a, b))}
+    out["width"] = width
+    out["form"] = form if tuner is None else "autotuned per level width"
+    out["timing"] = f"hipGraph of all levels, median of {reps} replays (hip events)"
+    return out
+
+
 def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
     """1024 independent instructions (40 % ADD/SUB, 20 % 8x8/16x16 array MUL,
     20 % LT/EQ, 20 % AND/OR/XOR; widths 8/16/32), gates of each level merged
@@ -326,12 +373,13 @@ def main():
         primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
 
     tuner = None
-    if not args.no_autotune and not (args.no_add and args.no_mixed and args.no_shift):
+    if not args.no_autotune and not (args.no_add and args.no_mixed and args.no_shift and args.no_seq):
         from paper_2101_03403_amd.autotune import Autotuner
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
     rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
+    rec_seq = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -356,6 +404,8 @@ def main():
         rec["mixed_stream"] = rec_mix
     if rec_shift is not None:
         rec["shift32"] = rec_shift
+    if rec_seq is not None:
+        rec["mul_div32"] = rec_seq
     if tuner is not None:
         rec["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner.measurements.get(b)}
                            for b, c in sorted(tuner.table.items())}
