@@ -29,9 +29,9 @@
 // wave per gadget digit, so the 6 forward transforms of a step run side by
 // side; each digit wave multiplies its spectrum by its own two key spectra
 // (prefetched into registers a step ahead), the partial products meet in
-// LDS, and two waves sum them in a fixed order and run the two inverse
-// transforms. A step then costs about three transform latencies instead of
-// eight.
+// LDS, all six waves sum them (in a fixed row order, each wave a share of
+// the frequency slots), and two waves run the two inverse transforms. A step
+// then costs about three transform latencies instead of eight.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -413,9 +413,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
 constexpr int LAT_WAVES = 6;   // one wave per digit row (2 components x l = 3)
 constexpr int LAT_EXT = 3 * FN; // negacyclic extension of one ACC component
 
-// Partial-product slot of (output q, digit row w): row q's own product for
-// output q stays in that wave's registers, so 10 of the 12 pairs need a slot.
-__device__ __forceinline__ int lat_slot(int q, int w) { return q == 0 ? w - 1 : 5 + (w == 0 ? 0 : w - 1); }
+constexpr int LAT_REGION = 2 * FH;  // d2 per wave: its two partial products, or its transpose scratch
 
 // ACC component c is kept as its negacyclic extension E_c[k], k < 3N:
 // E[k] = ACC[k] for k mod 2N < N and -ACC[k mod N] otherwise, so that
@@ -425,15 +423,18 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
                                                                       const uint16_t *__restrict__ bars, int32_t n,
                                                                       uint32_t *__restrict__ ext)
 {
+    static_assert(SCR <= LAT_REGION, "scratch fits a region");
     __shared__ uint32_t accx[2][LAT_EXT];
-    __shared__ d2 scr_all[LAT_WAVES][SCR];
-    __shared__ d2 part[10][FH];               // partial products (slot, slot*64 + lane)
+    // region of wave w: its transpose scratch during a transform, then its
+    // partial products (output q, slot*64 + lane) at q*FH; region 2 ends up
+    // holding the six-row sums
+    __shared__ d2 region[LAT_WAVES][LAT_REGION];
     const int tid = threadIdx.x, lane = tid & 63;
     const int p = tid >> 6;                    // digit row of this wave: component c, digit jj
     const int c = p / 3, jj = p - 3 * c;
     const uint32_t sh = (uint32_t)(32 - 7 * (jj + 1));
     const int64_t g = blockIdx.x;              // the grid has exactly one workgroup per gate
-    d2 *scr = scr_all[p];
+    d2 *scr = region[p];
     const uint16_t *bar = bars + g * (int64_t)(n + 1);
     const Tw t0 = make_tw(lane);
     Tw t = t0;
@@ -484,14 +485,14 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
         __builtin_amdgcn_sched_barrier(0);
         fft_fwd(x, scr, lane, t);
         __builtin_amdgcn_sched_barrier(0);
-        // partial products of this digit row with the two key spectra
-        d2 keep[8];
+        // partial products of this digit row with the two key spectra, into
+        // this wave's region (its transform is done; LDS ops of a wave are
+        // ordered)
+        wave_lds_fence();
         static_for<0, 8>([&](auto sI) {
             constexpr int sl = decltype(sI)::value;
-            const d2 pa = cmul(x[sl], kq[sl]);
-            const d2 pb = cmul(x[sl], kq[8 + sl]);
-            if (p == 0) keep[sl] = pa; else part[lat_slot(0, p)][sl * 64 + lane] = pa;
-            if (p == 1) keep[sl] = pb; else part[lat_slot(1, p)][sl * 64 + lane] = pb;
+            scr[sl * 64 + lane] = cmul(x[sl], kq[sl]);
+            scr[FH + sl * 64 + lane] = cmul(x[sl], kq[8 + sl]);
         });
         {   // prefetch the next step's key spectra (past the last step: step 0, unused)
             const int ni = i + 1 < n ? i + 1 : 0;
@@ -499,22 +500,23 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
             static_for<0, 16>([&](auto kI) { kq[decltype(kI)::value] = src[decltype(kI)::value * 64]; });
         }
         __syncthreads();   // partial products visible
-        if (p < 2) {
-            // output q = p: the six rows summed in row order, inverse transform,
-            // untwist, round, accumulate
-            d2 y[8];
-            {
-                const d2 *r0 = part[lat_slot(1, 0)] + lane, *r1 = part[lat_slot(0, 1)] + lane;
-                static_for<0, 8>([&](auto sI) {
-                    constexpr int sl = decltype(sI)::value;
-                    y[sl] = (p == 0 ? keep[sl] : r0[sl * 64]) + (p == 1 ? keep[sl] : r1[sl * 64]);
-                });
-            }
+        // the six rows summed in row order, (output, slot) pairs spread over
+        // the six waves (pairs p, p + 6, p + 12); the sum replaces row 2's
+        // term in place
 #pragma unroll
-            for (int w = 2; w < LAT_WAVES; ++w) {
-                const d2 *r = part[lat_slot(p, w)] + lane;
-                static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] += r[decltype(sI)::value * 64]; });
-            }
+        for (int k = p; k < 2 * 8; k += LAT_WAVES) {
+            const int e = (k >> 3) * FH + (k & 7) * 64 + lane;
+            d2 v = region[0][e] + region[1][e];
+#pragma unroll
+            for (int w = 2; w < LAT_WAVES; ++w) v += region[w][e];
+            region[2][e] = v;
+        }
+        __syncthreads();   // sums visible
+        if (p < 2) {
+            // output q = p: inverse transform, untwist, round and accumulate
+            // into ACC_q (scratch: this wave's own region, consumed above)
+            d2 y[8];
+            static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] = region[2][p * FH + decltype(sI)::value * 64 + lane]; });
             fft_inv(y, scr, lane, t);
             uint32_t *dst = accx[p] + lane;
             static_for<0, 8>([&](auto mI) {
