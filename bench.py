@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
     ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
     ap.add_argument("--no-shift", action="store_true", help="skip the 32-bit barrel-shifter latency measurement")
+    ap.add_argument("--no-emu", action="store_true", help="skip the emulator while-loop run")
     ap.add_argument("--no-seq", action="store_true",
                     help="skip the 32-bit sequential multiplier / divider latency measurement")
     ap.add_argument("--add-instances", type=int, default=256)
@@ -260,6 +261,34 @@ def sequential_units(keys, dev, form, width=32, reps=2, tuner=None):
     return out
 
 
+def emulator_while_loop(keys, dev, form, count=42, tuner=None):
+    """The paper's while loop (Sec. 6.1) on the emulator front-end: MOV R0,
+    #count; Loop: SUBS R0, R0, #1; B_NE Loop -- count encrypted 32-bit
+    subtractions with NZCV flags, each branch resolved by the client (the
+    secret-key holder) from the encrypted flags. Wall time of the whole run
+    including the client round trips; the paper reports 169.8 ms for the
+    32-bit flag unit alone and 1115 ms for a 32-bit SUB."""
+    import torch
+    from paper_2101_03403_amd import circuits as Cc, emulator as E
+
+    text = f"MOV R0, R0, #{count}\nLoop: SUBS R0, R0, #1\nB_NE Loop\n"
+    client = E.make_client(keys)
+    warm = E.Machine(keys, width=32, form=form, tuner=tuner, device=dev)
+    warm.run(text.replace(f"#{count}", "#1"), client)          # builds the units, tunes their widths
+    mach = E.Machine(keys, width=32, form=form, tuner=tuner, device=dev)
+    mach._units = warm._units
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = mach.run(text, client)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r0 = Cc.bits_to_int(keys.decrypt(mach.read_register(0)))
+    return {"iterations": count, "wall_ms": wall * 1e3, "ms_per_iteration": wall * 1e3 / count,
+            "instructions": stats["instructions"], "branches": stats["branches"],
+            "bootstraps": stats["bootstraps"], "levels": stats["levels"], "r0_decrypts_to_zero": int(r0 == 0),
+            "form": form if tuner is None else "autotuned per level width"}
+
+
 def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
     """1024 independent instructions (40 % ADD/SUB, 20 % 8x8/16x16 array MUL,
     20 % LT/EQ, 20 % AND/OR/XOR; widths 8/16/32), gates of each level merged
@@ -373,13 +402,14 @@ def main():
         primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
 
     tuner = None
-    if not args.no_autotune and not (args.no_add and args.no_mixed and args.no_shift and args.no_seq):
+    if not args.no_autotune and not (args.no_add and args.no_mixed and args.no_shift and args.no_seq and args.no_emu):
         from paper_2101_03403_amd.autotune import Autotuner
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
     rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
     rec_seq = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner)
+    rec_emu = None if args.no_emu else emulator_while_loop(keys, dev, args.form, tuner=tuner)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -406,6 +436,8 @@ def main():
         rec["shift32"] = rec_shift
     if rec_seq is not None:
         rec["mul_div32"] = rec_seq
+    if rec_emu is not None:
+        rec["emulator_while_loop"] = rec_emu
     if tuner is not None:
         rec["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner.measurements.get(b)}
                            for b, c in sorted(tuner.table.items())}

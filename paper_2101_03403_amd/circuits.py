@@ -371,6 +371,39 @@ def nonrestoring_divide(c: Circuit, Q: list, D: list) -> list:
     return Q
 
 
+def or_reduce(c: Circuit, bits: list) -> int:
+    """Balanced OR tree (log2 W levels, W/2 gates in the first)."""
+    layer = list(bits)
+    while len(layer) > 1:
+        nxt = [c.gate(OR, layer[i], layer[i + 1]) for i in range(0, len(layer) - 1, 2)]
+        if len(layer) % 2:
+            nxt.append(layer[-1])
+        layer = nxt
+    return layer[0]
+
+
+def nzcv_flags(c: Circuit, result: list, carry: int | None = None, a_msb: int | None = None,
+               b_msb: int | None = None) -> list:
+    """Conditional flags of Sec. 6.1, as wires [N, Z, C, V]: N = the result's
+    MSB (a copy); Z = NOT of the OR reduction of the result; C = the adder's
+    carry-out (constant 0 when there is none); V = (NOT a . NOT b . s) +
+    (a . b . NOT s) on the sign bits of the adder's two operands and of the
+    result (constant 0 without operands). Z and V are the bootstrapped part,
+    evaluated side by side."""
+    W = len(result)
+    s = result[W - 1]
+    n_flag = s
+    z_flag = c.NOT(or_reduce(c, result))
+    c_flag = carry if carry is not None else c.const(0)
+    if a_msb is None:
+        v_flag = c.const(0)
+    else:
+        both_clear = c.gate(NOR, a_msb, b_msb)
+        both_set = c.gate(AND, a_msb, b_msb)
+        v_flag = c.gate(OR, c.gate(AND, both_clear, s), c.gate(ANDYN, both_set, s))
+    return [n_flag, z_flag, c_flag, v_flag]
+
+
 def adder_instance(width: int, carry_in_one: bool = False):
     """A standalone W-bit ADD (or SUB if carry_in_one and inputs negated by the
     caller) circuit: inputs a[0..W), b[0..W); output 'sum'."""
@@ -545,6 +578,40 @@ class Program:
         return g
 
 
+def flag_setting_circuit(kind: str, width: int) -> Circuit:
+    """ADDS / SUBS (and CMP, which is SUBS without a destination): outputs
+    'out' (the W-bit result) and 'nzcv' (the four flags, Sec. 6.1). For
+    SUBS, C = 1 means no borrow (a >= b unsigned) and V is taken on the
+    adder's operands a and NOT b, as in the ARM definition."""
+    c = Circuit()
+    A = c.inputs_word(width)
+    B = c.inputs_word(width)
+    if kind == "ADDS":
+        out, carry = kogge_stone_add(c, A, B)
+        b_top = B[width - 1]
+    elif kind in ("SUBS", "CMP"):
+        out, carry = subtract(c, A, B)
+        b_top = c.NOT(B[width - 1])
+    else:
+        raise ValueError(f"unknown flag-setting instruction {kind}")
+    c.outputs["out"] = out
+    c.outputs["nzcv"] = nzcv_flags(c, out, carry, A[width - 1], b_top)
+    return c
+
+
+def nzcv_reference(kind: str, width: int, a: int, b: int) -> list:
+    """Cleartext [N, Z, C, V] of ADDS / SUBS / CMP on W-bit operands."""
+    m = (1 << width) - 1
+    sa = a - (1 << width) if a >> (width - 1) else a
+    sb = b - (1 << width) if b >> (width - 1) else b
+    if kind == "ADDS":
+        r, cflag, sr = (a + b) & m, int(a + b > m), sa + sb
+    else:
+        r, cflag, sr = (a - b) & m, int(a >= b), sa - sb
+    vflag = int(sr < -(1 << (width - 1)) or sr >= (1 << (width - 1)))
+    return [r >> (width - 1), int(r == 0), cflag, vflag]
+
+
 def instruction_circuit(kind: str, width: int) -> Circuit:
     """One instruction as a circuit with inputs a, b (width bits each, LSB
     first) and output 'out'. Shifts (LLS / LRS / ARS) are register mode: b is
@@ -572,6 +639,8 @@ def instruction_circuit(kind: str, width: int) -> Circuit:
         out = sequential_multiply(c, A, B, signed=True)
     elif kind == "DIV":
         out = nonrestoring_divide(c, A, B)
+    elif kind == "ORN":
+        out = bitwise(c, ORYN, A, B)
     else:
         raise ValueError(f"unknown instruction {kind}")
     c.outputs["out"] = out
@@ -596,4 +665,4 @@ def instruction_result(kind: str, width: int, a: int, b: int) -> int:
     if kind == "DIV":
         return a // b if b else m
     return {"ADD": (a + b) & m, "SUB": (a - b) & m, "MUL": a * b, "MULSEQ": a * b, "LT": int(a < b),
-            "EQ": int(a == b), "AND": a & b, "OR": a | b, "XOR": a ^ b}[kind]
+            "EQ": int(a == b), "AND": a & b, "OR": a | b, "XOR": a ^ b, "ORN": (a | (~b & m)) & m}[kind]

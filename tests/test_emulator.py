@@ -1,0 +1,216 @@
+"""Emulator front-end (Sec. 4, 6): assembler, condition codes, NZCV flag
+circuits on the CPU; whole programs on the GPU against a cleartext
+interpreter written here."""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2101_03403_amd import circuits as C
+from paper_2101_03403_amd import emulator as E
+
+WHILE_LOOP = """
+    MOV    R0    R0    {n}
+Loop_label:
+    SUBS   R0    R0    1
+    B_NE   Loop_label
+"""
+
+
+def test_assemble_while_loop():
+    prog, labels = E.assemble(WHILE_LOOP.format(n=42))
+    assert [i.op for i in prog] == ["MOV", "SUBS", "B"]
+    assert labels == {"Loop_label": 1}
+    assert prog[0].rd == 0 and prog[0].imm == 42
+    assert prog[1].rd == 0 and prog[1].rn == 0 and prog[1].imm == 1 and prog[1].rm == -1
+    assert prog[2].cond == "NE" and prog[2].target == "Loop_label"
+
+
+def test_assemble_forms_and_errors():
+    prog, labels = E.assemble("""
+        LOAD R1, 0        ; comment
+        start: ADD R2, R1, R1
+        LSL R3 R2 #3      // immediate shift
+        LLS R3 R2 R1
+        CMP R3, 0x10
+        B_LT start
+        MOV R4, R3
+        MVN R5 R4
+        STORE R5 1
+        HALT
+    """)
+    assert labels == {"start": 1}
+    assert prog[2].imm == 3 and prog[3].rm == 1 and prog[4].imm == 16 and prog[6].rm == 3
+    with pytest.raises(ValueError):
+        E.assemble("FOO R1 R2 R3")
+    with pytest.raises(ValueError):
+        E.assemble("B nowhere")
+    with pytest.raises(ValueError):
+        E.assemble("B_XX here\nhere: HALT")
+
+
+def test_condition_codes_against_signed_unsigned_compare():
+    """After CMP a, b the ARM conditions equal the integer comparisons."""
+    w = 4
+    for a, b in itertools.product(range(16), repeat=2):
+        n, z, c, v = C.nzcv_reference("CMP", w, a, b)
+        sa = a - 16 if a >= 8 else a
+        sb = b - 16 if b >= 8 else b
+        want = {"EQ": a == b, "NE": a != b, "CS": a >= b, "CC": a < b, "HI": a > b, "LS": a <= b,
+                "GE": sa >= sb, "LT": sa < sb, "GT": sa > sb, "LE": sa <= sb, "AL": True}
+        for cond, val in want.items():
+            assert E.condition_holds(cond, n, z, c, v) == val, (a, b, cond)
+
+
+@pytest.mark.parametrize("kind", ["ADDS", "SUBS"])
+def test_flag_circuits_exhaustive_4bit(kind):
+    c = C.flag_setting_circuit(kind, 4)
+    for a, b in itertools.product(range(16), repeat=2):
+        v = c.eval_plain(C.int_to_bits(a, 4) + C.int_to_bits(b, 4))
+        assert [int(x) for x in v[c.outputs["nzcv"]]] == C.nzcv_reference(kind, 4, a, b)
+        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result("ADD" if kind == "ADDS" else "SUB", 4, a, b)
+
+
+def test_flag_circuits_32bit_random():
+    rng = np.random.default_rng(3)
+    for kind in ("ADDS", "SUBS"):
+        c = C.flag_setting_circuit(kind, 32)
+        cases = [(0, 0), (2**31, 2**31), (2**31 - 1, 1), (5, 5), (0, 1)]
+        cases += [tuple(int(x) for x in rng.integers(0, 2**32, 2, dtype=np.uint64)) for _ in range(30)]
+        for a, b in cases:
+            v = c.eval_plain(C.int_to_bits(a, 32) + C.int_to_bits(b, 32))
+            assert [int(x) for x in v[c.outputs["nzcv"]]] == C.nzcv_reference(kind, 32, a, b), (kind, a, b)
+
+
+# ------------------------------------------------------------------ cleartext interpreter (test reference)
+def interpret(text, width, mem, max_steps=10000):
+    prog, labels = E.assemble(text)
+    m = (1 << width) - 1
+    regs = [0] * 16
+    mem = list(mem)
+    flags = (0, 0, 0, 0)
+    pc = steps = 0
+    while 0 <= pc < len(prog) and steps < max_steps:
+        ins = prog[pc]
+        steps += 1
+        nxt = pc + 1
+        op2 = lambda: regs[ins.rm] if ins.rm >= 0 else ins.imm & m  # noqa: E731
+        if ins.op == "HALT":
+            break
+        if ins.op == "MOV":
+            regs[ins.rd] = regs[ins.rm] if ins.rm >= 0 else ins.imm & m
+        elif ins.op == "MVN":
+            regs[ins.rd] = ~regs[ins.rm] & m
+        elif ins.op == "LOAD":
+            regs[ins.rd] = mem[ins.imm]
+        elif ins.op == "STORE":
+            mem[ins.imm] = regs[ins.rd]
+        elif ins.op == "B":
+            if E.condition_holds(ins.cond, *flags):
+                nxt = labels[ins.target]
+        elif ins.op in E.FLAG_KINDS:
+            kind = E.FLAG_KINDS[ins.op]
+            a, b = regs[ins.rn], op2()
+            flags = tuple(C.nzcv_reference(kind, width, a, b))
+            if ins.op != "CMP":
+                regs[ins.rd] = C.instruction_result("ADD" if kind == "ADDS" else "SUB", width, a, b)
+        else:
+            kind = E.ALU_KINDS[ins.op]
+            regs[ins.rd] = C.instruction_result(kind, width, regs[ins.rn], op2()) & m
+        pc = nxt
+    return regs, mem, flags, steps
+
+
+torch = None
+
+
+@pytest.fixture(scope="module")
+def gpu_keys():
+    global torch
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2101_03403_amd import cemu, workloads as W
+    print("[gpu] emulator keygen", flush=True)
+    return cemu.keygen(cemu.STD, W.KEY_SEED)
+
+
+@pytest.mark.gpu
+def test_while_loop_end_to_end(gpu_keys):
+    """The paper's while loop (Sec. 6.1) on encrypted data: i counts down to
+    0, the branch is resolved by the client from the encrypted Z flag."""
+    from paper_2101_03403_amd import cemu
+    keys = gpu_keys
+    sys.stdout.flush()
+    calls = []
+    client = E.make_client(keys)
+
+    def counting_client(cond, nzcv):
+        calls.append(cond)
+        return client(cond, nzcv)
+
+    saved = cemu.get_tuning(keys)
+    try:
+        cemu.set_tuning(keys, fft_gates_per_wg=1)
+        mach = E.Machine(keys, width=32)
+        stats = mach.run(WHILE_LOOP.format(n=5), counting_client)
+    finally:
+        cemu.set_tuning(keys, **saved)
+    assert C.bits_to_int(keys.decrypt(mach.read_register(0))) == 0
+    assert calls == ["NE"] * 5
+    assert stats["instructions"] == 1 + 2 * 5
+    assert [int(x) for x in keys.decrypt(mach.read_flags())] == [0, 1, 1, 0]   # 1 - 1: Z and C (no borrow)
+
+
+@pytest.mark.gpu
+def test_program_covers_instruction_classes(gpu_keys):
+    """8-bit machine: loads, every data-processing instruction in register
+    and immediate form, flags, a counted loop with a signed branch, stores;
+    decrypted memory and registers equal the cleartext interpreter."""
+    from paper_2101_03403_amd import cemu, workloads as W
+    keys = gpu_keys
+    width = 8
+    text = """
+        LOAD R1, 0
+        LOAD R2, 1
+        ADD  R3, R1, R2
+        SUB  R4, R1, R2
+        MUL  R5, R1, R2
+        UDIV R6, R1, R2
+        AND  R7, R1, R2
+        ORR  R8, R1, #0x0F
+        EOR  R9, R1, R2
+        ORN  R10, R1, R2
+        LSL  R11, R1, R2
+        LSR  R12, R1, #3
+        ASR  R13, R1, R2
+        MVN  R14, R2
+        MOV  R15, R15, #0
+    loop:
+        ADDS R15, R15, #7
+        CMP  R15, #30
+        B_LT loop
+        STORE R3, 2
+        STORE R4, 3
+        STORE R5, 4
+        STORE R6, 5
+        STORE R15, 6
+        HALT
+    """
+    mem = [0xB5, 0x03, 0, 0, 0, 0, 0, 0]
+    regs_ref, mem_ref, flags_ref, _ = interpret(text, width, mem)
+    saved = cemu.get_tuning(keys)
+    try:
+        cemu.set_tuning(keys, fft_gates_per_wg=1)
+        mach = E.Machine(keys, width=width, mem_words=len(mem))
+        bits = np.array([C.int_to_bits(v, width) for v in mem], np.uint8).reshape(-1)
+        mach.write_memory(keys.encrypt(bits, seed=W.ENC_SEED + 31).reshape(len(mem), width, -1))
+        mach.run(text, E.make_client(keys))
+    finally:
+        cemu.set_tuning(keys, **saved)
+    got_mem = [C.bits_to_int(keys.decrypt(w)) for w in mach.read_memory()]
+    assert got_mem == mem_ref
+    for r in range(16):
+        assert C.bits_to_int(keys.decrypt(mach.read_register(r))) == regs_ref[r], f"R{r}"
+    assert tuple(int(x) for x in keys.decrypt(mach.read_flags())) == flags_ref
