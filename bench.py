@@ -329,6 +329,18 @@ def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
 FFT_KERNEL = {8: "br_fft_kernel<8>", 4: "br_fft_kernel<4>", 1: "br_fft_lat_kernel"}
 
 
+def output_noise(keys, out, want):
+    """Phase error of the bootstrapped outputs against +-1/8, measured with
+    the secret key (in torus units, 1 = 2^32): decryption stays exact while
+    |error| < 1/8."""
+    ph = keys.phase(out).astype(np.int64)
+    mu = np.where(want == 1, 1 << 29, (1 << 32) - (1 << 29))
+    e = (ph - mu) % (1 << 32)
+    e = np.where(e >= 1 << 31, e - (1 << 32), e) / float(1 << 32)
+    return {"std": float(np.std(e)), "max_abs": float(np.max(np.abs(e))), "log2_std": float(np.log2(np.std(e))),
+            "margin": 0.125}
+
+
 def roofline(form, prof, B, fft_gates_per_wg=8):
     if form == "int8":
         ms, cnt = prof["blind_rotate_int8"]
@@ -395,6 +407,7 @@ def main():
             "roofline": roofline(form, prof, B, args.fft_gates_per_wg),
             "kernels": {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()},
             "decrypt_exact": f"{int(np.sum(keys.decrypt(host) == want))}/{B}",
+            "output_noise": output_noise(keys, host, want),
         }
     primary = res[args.form]
     if len(outs) == 2:
