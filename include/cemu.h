@@ -146,7 +146,10 @@ int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int
  * unspecified ciphertext. B = 0 is a no-op. Scratch: the library keeps
  * per-cloud-key device workspaces sized for the largest B seen (allocated on
  * demand, so this call may allocate). Calls sharing one cloud key must not
- * overlap in time on different streams.
+ * overlap in time on different streams. A hipGraph captured around these
+ * calls records the workspace addresses: size the workspaces first (run the
+ * same launches once eagerly), and replay the graph only while no later call
+ * on the same cloud key has needed a larger workspace (that reallocates it).
  * Errors: CEMU_ERR_NULL, CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0),
  * CEMU_ERR_PARAM (unknown form), CEMU_ERR_OOM, CEMU_ERR_HIP. */
 int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,

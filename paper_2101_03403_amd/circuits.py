@@ -565,7 +565,9 @@ class Program:
     def capture(self, keys, pool, form="fft64", tuner=None):
         """Capture the level sequence as one hipGraph (after an eager run has
         sized the library's workspaces and, with a tuner, tuned every level
-        width). Returns the torch graph object."""
+        width). Returns the torch graph object. The graph records the cloud
+        key's workspace addresses, so it stays valid only until a call on the
+        same key needs a larger batch than this program's widest level."""
         import torch
         stream = torch.cuda.Stream()
         torch.cuda.synchronize()
