@@ -151,7 +151,9 @@ int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int
  * same launches once eagerly), and replay the graph only while no later call
  * on the same cloud key has needed a larger workspace (that reallocates it).
  * Errors: CEMU_ERR_NULL, CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0),
- * CEMU_ERR_PARAM (unknown form), CEMU_ERR_OOM, CEMU_ERR_HIP. */
+ * CEMU_ERR_PARAM (unknown form), CEMU_ERR_UNSUPPORTED (FFT64 form with
+ * N != 1024: it is built for the standard ring degree only), CEMU_ERR_OOM,
+ * CEMU_ERR_HIP. */
 int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
                          const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out,
                          int64_t B, void *hip_stream);

@@ -157,10 +157,15 @@ def test_std_batch_sampled_bit_exact(std, dev):
     assert np.array_equal(out[idx], oout)
 
 
-def test_key_switch_alone(std, dev):
+@pytest.mark.parametrize("B", [1, 37, 300, 1600])
+def test_key_switch_alone(std, dev, B):
+    """Key switching alone, bit-exact against the oracle, across the launch
+    shapes: K split over 32 (B = 1, 37), 16 (300) and 4 (1600) workgroups per
+    tile with integer-atomic sums (B = 4096, unsplit, is covered by the gate
+    tests)."""
     lk, ok = std
-    rng = np.random.default_rng(7)
-    B = 37
+    say(f"[gpu] key switch B={B}")
+    rng = np.random.default_rng(7 + B)
     ins = rng.integers(0, 1 << 32, (B, lk.N + 1), dtype=np.uint64).astype(np.uint32)
     din = to_dev(ins, dev)
     dout = torch.zeros((B, lk.n + 1), dtype=torch.int32, device=dev)
@@ -227,6 +232,13 @@ def test_not_copy_constant(toy, dev):
 def test_errors_are_reported(toy, dev):
     lk, _ = toy
     z = torch.zeros(4, dtype=torch.int32, device=dev)
+    # the FFT64 form is built for N = 1024 only: the toy set (N = 512) is refused
+    ops = torch.zeros(2, dtype=torch.uint8, device=dev)
+    pool = torch.zeros((2, lk.n + 1), dtype=torch.int32, device=dev)
+    rows = torch.arange(2, dtype=torch.int32, device=dev)
+    with pytest.raises(cemu.CemuError) as exc:
+        cemu.bootstrap_gates(lk, ops, pool, rows, rows, pool, form="fft64")
+    assert exc.value.code == -6            # CEMU_ERR_UNSUPPORTED
     with pytest.raises(cemu.CemuError):
         cemu._check(cemu.lib().cemu_bootstrap_gates(lk.ck, 7, None, None, None, None, None, None, 4, None))
     with pytest.raises(cemu.CemuError):
