@@ -1,8 +1,10 @@
 // Device part of libcemu for gfx950 (MI355X): key upload, the gate
-// linear-combination + modulus-switch kernel, the blind-rotation kernels
-// (int8-MFMA form in cemu_br_int8.hip, FFT64 form in cemu_br_fft.hip), the
-// key-switching kernel, the unbootstrapped NOT / COPY / CONSTANT kernels, and
-// the device entry points of the C ABI.
+// linear-combination + modulus-switch kernel, the two halves of the
+// homomorphic MUX (its lincomb over 2B gates and the combine of the two
+// extracted samples), the blind-rotation kernels (int8-MFMA form in
+// cemu_br_int8.hip, FFT64 form in cemu_br_fft.hip), the key-switching
+// kernels (MFMA form in cemu_ks.hip, VALU form here), the unbootstrapped
+// NOT / COPY / CONSTANT kernels, and the device entry points of the C ABI.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
