@@ -129,10 +129,11 @@ def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
     return wall, cemu.profile_read(keys)
 
 
-def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None):
+def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="gates"):
     """32-bit Kogge-Stone ADD (Sec. 5.2): `instances` concurrent ADDs with all
-    gates of a level in one launch, the 12 levels captured as one hipGraph.
-    Latency = first level launch to last level done; also one instance alone."""
+    gates of a level in one launch, the levels (12 with the paper's AND/OR
+    prefix, 7 with the MUX prefix) captured as one hipGraph. Latency = first
+    level launch to last level done; also one instance alone."""
     import torch
     from paper_2101_03403_amd import circuits as Cc, workloads as W
 
@@ -140,7 +141,7 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None):
     for inst in (instances, 1):
         rng = np.random.default_rng(404 + inst)
         ops = rng.integers(0, 1 << 32, (inst, 2), dtype=np.uint64)
-        cs = [Cc.adder_instance(32) for _ in range(inst)]
+        cs = [Cc.adder_instance(32, prefix=prefix) for _ in range(inst)]
         prog = Cc.Program(cs).to_device(dev)
         bits = []
         for a, b in ops:
@@ -169,10 +170,13 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None):
         ms = float(np.median(times))
         key = "batch" if inst == instances else "single"
         out[key] = {"instances": inst, "latency_ms": ms, "amortized_ms_per_add": ms / inst,
-                    "gates": prog.num_gates(), "levels": prog.depth, "gates_per_s": prog.num_gates() / (ms * 1e-3),
-                    "decrypt_exact": f"{ok}/{inst}", "level_widths": prog.level_widths()}
+                    "gates": prog.num_gates(), "muxes": prog.num_muxes(), "bootstraps": prog.num_bootstraps(),
+                    "levels": prog.depth, "bootstraps_per_s": prog.num_bootstraps() / (ms * 1e-3),
+                    "decrypt_exact": f"{ok}/{inst}", "level_widths": prog.level_widths(),
+                    "level_muxes": prog.level_mux_counts()}
+    out["prefix"] = {"gates": "the paper's AND/OR o operator", "mux": "one MUX per o carry"}[prefix]
     out["form"] = form if tuner is None else "autotuned per level width"
-    out["timing"] = "hipGraph of the 12 level launches, median of 3 replays (hip events)"
+    out["timing"] = f"hipGraph of the level launches, median of {reps} replays (hip events)"
     return out
 
 
@@ -216,7 +220,7 @@ def shift32_latency(keys, dev, form, reps=3, tuner=None):
     return out
 
 
-def sequential_units(keys, dev, form, width=32, reps=2, tuner=None):
+def sequential_units(keys, dev, form, width=32, reps=2, tuner=None, prefix="gates"):
     """The paper's sequential multiplier (unsigned and signed) and the
     non-restoring divider (Sec. 5.5, 5.6), one instance each: W iterations
     of a W- or (W+1)-bit adder, hundreds of narrow levels, captured as a
@@ -233,7 +237,7 @@ def sequential_units(keys, dev, form, width=32, reps=2, tuner=None):
         b = int(rng.integers(1, 1 << width, dtype=np.uint64))
         if kind == "DIV":
             b = int(rng.integers(1, 1 << (width // 2)))
-        c = Cc.instruction_circuit(kind, width)
+        c = Cc.instruction_circuit(kind, width, prefix=prefix)
         prog = Cc.Program([c]).to_device(dev)
         pool = torch.zeros((prog.rows, keys.n + 1), dtype=torch.int32, device=dev)
         enc = keys.encrypt(np.asarray(Cc.int_to_bits(a, width) + Cc.int_to_bits(b, width), np.uint8),
@@ -253,15 +257,16 @@ def sequential_units(keys, dev, form, width=32, reps=2, tuner=None):
             times.append(e0.elapsed_time(e1))
         host = pool.cpu().numpy().view(np.uint32)
         got = Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"])]))
-        out[kind] = {"latency_ms": float(np.median(times)), "gates": prog.num_gates(), "levels": prog.depth,
-                     "decrypt_exact": int(got == Cc.instruction_result(kind, width, a, b))}
+        out[kind] = {"latency_ms": float(np.median(times)), "gates": prog.num_gates(), "muxes": prog.num_muxes(),
+                     "levels": prog.depth, "decrypt_exact": int(got == Cc.instruction_result(kind, width, a, b))}
     out["width"] = width
+    out["prefix"] = {"gates": "the paper's AND/OR o operator", "mux": "one MUX per o carry"}[prefix]
     out["form"] = form if tuner is None else "autotuned per level width"
     out["timing"] = f"hipGraph of all levels, median of {reps} replays (hip events)"
     return out
 
 
-def emulator_while_loop(keys, dev, form, count=42, tuner=None):
+def emulator_while_loop(keys, dev, form, count=42, tuner=None, prefix="gates"):
     """The paper's while loop (Sec. 6.1) on the emulator front-end: MOV R0,
     #count; Loop: SUBS R0, R0, #1; B_NE Loop -- count encrypted 32-bit
     subtractions with NZCV flags, each branch resolved by the client (the
@@ -273,9 +278,9 @@ def emulator_while_loop(keys, dev, form, count=42, tuner=None):
 
     text = f"MOV R0, R0, #{count}\nLoop: SUBS R0, R0, #1\nB_NE Loop\n"
     client = E.make_client(keys)
-    warm = E.Machine(keys, width=32, form=form, tuner=tuner, device=dev)
+    warm = E.Machine(keys, width=32, form=form, tuner=tuner, device=dev, prefix=prefix)
     warm.run(text.replace(f"#{count}", "#1"), client)          # builds the units, tunes their widths
-    mach = E.Machine(keys, width=32, form=form, tuner=tuner, device=dev)
+    mach = E.Machine(keys, width=32, form=form, tuner=tuner, device=dev, prefix=prefix)
     mach._units = warm._units
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -286,6 +291,7 @@ def emulator_while_loop(keys, dev, form, count=42, tuner=None):
     return {"iterations": count, "wall_ms": wall * 1e3, "ms_per_iteration": wall * 1e3 / count,
             "instructions": stats["instructions"], "branches": stats["branches"],
             "bootstraps": stats["bootstraps"], "levels": stats["levels"], "r0_decrypts_to_zero": int(r0 == 0),
+            "prefix": {"gates": "the paper's AND/OR o operator", "mux": "one MUX per o carry"}[prefix],
             "form": form if tuner is None else "autotuned per level width"}
 
 
@@ -419,10 +425,13 @@ def main():
         from paper_2101_03403_amd.autotune import Autotuner
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
+    rec_add_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux")
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
     rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
     rec_seq = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner)
+    rec_seq_mux = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner, prefix="mux")
     rec_emu = None if args.no_emu else emulator_while_loop(keys, dev, args.form, tuner=tuner)
+    rec_emu_mux = None if args.no_emu else emulator_while_loop(keys, dev, args.form, tuner=tuner, prefix="mux")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -443,14 +452,17 @@ def main():
     }
     if rec_add is not None:
         rec["add32"] = rec_add
+        rec["add32_mux_prefix"] = rec_add_mux
     if rec_mix is not None:
         rec["mixed_stream"] = rec_mix
     if rec_shift is not None:
         rec["shift32"] = rec_shift
     if rec_seq is not None:
         rec["mul_div32"] = rec_seq
+        rec["mul_div32_mux_prefix"] = rec_seq_mux
     if rec_emu is not None:
         rec["emulator_while_loop"] = rec_emu
+        rec["emulator_while_loop_mux_prefix"] = rec_emu_mux
     if tuner is not None:
         rec["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner.measurements.get(b)}
                            for b, c in sorted(tuner.table.items())}

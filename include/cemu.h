@@ -183,6 +183,29 @@ int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *ou
 int cemu_mux(const cemu_cloud_key *ck, int form, const uint32_t *pool_in, const int32_t *is, const int32_t *ia,
              const int32_t *ib, const int32_t *io, uint32_t *pool_out, int64_t B, void *hip_stream);
 
+/* One circuit level that mixes bootstrapped gates and multiplexers (Table
+ * "TFHEbenchmark" gates and MUX; the gates of one level are independent,
+ * Sec. 5.2): G gates as cemu_bootstrap_gates and M MUXes as cemu_mux, with
+ * all G + 2M blind rotations in one launch and the G + M key switches in
+ * another, so a level costs one blind-rotation latency whatever its mix.
+ *   pool_in:   device uint32_t [P_in][n+1]
+ *   ops, ia, ib: device [G] (uint8_t op codes, int32_t rows), may be NULL
+ *             when G = 0
+ *   ms, ma, mb: device int32_t [M] rows of the selectors and of the inputs
+ *             chosen when the selector is true (ma) or false (mb), may be
+ *             NULL when M = 0
+ *   io:       device int32_t [G + M] output rows, gates first, then MUXes
+ *             (or NULL: output k goes to row k); rows must be distinct
+ *   pool_out, stream, alignment: as cemu_bootstrap_gates.
+ * Every output equals what cemu_bootstrap_gates (k < G) or cemu_mux
+ * (k >= G) computes for the same inputs, bit for bit. G = M = 0 is a no-op.
+ * Scratch: the workspaces hold G + 2M blind-rotation samples.
+ * Errors: CEMU_ERR_RANGE (G < 0 or M < 0), the others as
+ * cemu_bootstrap_gates. */
+int cemu_bootstrap_level(const cemu_cloud_key *ck, int form, const uint32_t *pool_in, const uint8_t *ops,
+                         const int32_t *ia, const int32_t *ib, int64_t G, const int32_t *ms, const int32_t *ma,
+                         const int32_t *mb, int64_t M, const int32_t *io, uint32_t *pool_out, void *hip_stream);
+
 /* Unbootstrapped operations of Table "TFHEbenchmark" on a device pool
  * [P][n+1]: NOT (negation of every word), COPY, and CONSTANT (trivial
  * ciphertext (0,...,0, +-1/8)). src, dst: device int32_t [count] rows; for

@@ -53,7 +53,7 @@ class Params(C.Structure):
 EXPORTED = [
     "cemu_params_default", "cemu_keygen", "cemu_secret_params", "cemu_cloud_params", "cemu_encrypt",
     "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates",
-    "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_mux", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
+    "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_mux", "cemu_bootstrap_level", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
     "cemu_profile_enable", "cemu_profile_read", "cemu_get_tuning", "cemu_set_tuning",
 ]
@@ -84,6 +84,7 @@ def lib() -> C.CDLL:
     L.cemu_blind_rotate_extract.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_key_switch.argtypes = [vp, vp, vp, i64, vp]
     L.cemu_mux.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.cemu_bootstrap_level.argtypes = [vp, C.c_int, vp, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.cemu_lwe_not.argtypes = [i32, vp, vp, vp, vp, i64, vp]
     L.cemu_lwe_copy.argtypes = [i32, vp, vp, vp, vp, i64, vp]
     L.cemu_lwe_constant.argtypes = [i32, vp, vp, vp, i64, vp]
@@ -266,6 +267,19 @@ def mux(keys: Keys, pool_in, isel, ia, ib, pool_out, io=None, form="int8", strea
     B = int(isel.shape[0])
     _check(lib().cemu_mux(keys.ck, FORMS[form], _dptr(pool_in), _dptr(isel), _dptr(ia), _dptr(ib), _dptr(io),
                           _dptr(pool_out), B, _stream(stream)))
+
+
+def bootstrap_level(keys: Keys, pool_in, gates, muxes, pool_out, io=None, form="int8", stream=None):
+    """A circuit level of G gates and M MUXes in one blind-rotation launch;
+    gates = (ops, ia, ib) or None, muxes = (isel, ia, ib) or None, io = output
+    rows [G + M] (gates first); see cemu_bootstrap_level in include/cemu.h."""
+    ops, ia, ib = gates if gates is not None else (None, None, None)
+    ms, ma, mb = muxes if muxes is not None else (None, None, None)
+    G = int(ops.shape[0]) if ops is not None else 0
+    M = int(ms.shape[0]) if ms is not None else 0
+    _check(lib().cemu_bootstrap_level(keys.ck, FORMS[form], _dptr(pool_in), _dptr(ops), _dptr(ia), _dptr(ib), G,
+                                      _dptr(ms), _dptr(ma), _dptr(mb), M, _dptr(io), _dptr(pool_out),
+                                      _stream(stream)))
 
 
 def lwe_not(n: int, pool_in, src, pool_out, dst, stream=None):

@@ -136,15 +136,58 @@ class Circuit:
 
 
 # ------------------------------------------------------------------ circuits
-def kogge_stone_add(c: Circuit, A: list, B: list, carry_in: int | None = None):
+# Forms of the adders' prefix stage: the paper's o operator as AND -> OR
+# gates (two levels per prefix level), or as one FHE MUX per carry (one level
+# per prefix level).
+PREFIX_GATES, PREFIX_MUX = "gates", "mux"
+
+
+def _prefix_mux(c: Circuit, G: list, P: list, first: int) -> int:
+    """MUX form of the prefix stage, in place on G, P (P[i] None = known 0).
+
+    Because g_i = a_i AND b_i and p_i = a_i XOR b_i never hold together, and
+    the o operator keeps that true for every group, the carry half of
+    (G_x, P_x) o (G_y, P_y) = (G_x + P_x G_y, P_x P_y) is a selection:
+    P_x ? G_y : G_x, one FHE MUX (Table "TFHEbenchmark") instead of AND -> OR.
+    Prefix level k (distance d = 2^(k-1)) runs at level first + k, its MUXes
+    beside the ANDs of the propagates that a later level still needs
+    (positions >= 2d). Returns the number of prefix levels."""
+    n = len(G)
+    d, k = 1, 1
+    while d < n:
+        newG = {i: G[i] if P[i] is None else c.mux(P[i], G[i - d], G[i], first + k) for i in range(d, n)}
+        newP = {i: None if P[i] is None or P[i - d] is None else c.gate(AND, P[i], P[i - d], first + k)
+                for i in range(2 * d, n)}
+        for i in range(d, n):
+            G[i] = newG[i]
+            P[i] = newP.get(i)
+        d *= 2
+        k += 1
+    return k - 1
+
+
+def kogge_stone_add(c: Circuit, A: list, B: list, carry_in: int | None = None, prefix: str = PREFIX_GATES):
     """Parallel-prefix adder (Sec. 5.2). A, B: wires, LSB first. carry_in:
     None (0) or 1 (constant). Returns (sum wires, carry-out wire).
 
-    Stages relative to the inputs' level: 1 = (g, p); for prefix level k
-    (distance 2^(k-1)): 2k = the two ANDs of every o, 2k+1 = its OR; last =
-    the sum XORs."""
+    prefix = PREFIX_GATES (the paper's structure): stages relative to the
+    inputs' level: 1 = (g, p); for prefix level k (distance 2^(k-1)): 2k = the
+    two ANDs of every o, 2k+1 = its OR; last = the sum XORs.
+    prefix = PREFIX_MUX: every o's carry is one MUX (see _prefix_mux), so a
+    W-bit adder is log2 W + 2 levels deep (7 for W = 32 instead of 12); with
+    carry-in 1 the carry out of bit 0 is a_0 OR b_0, taken in stage 1."""
     W = len(A)
     base = max(c.lv[w] for w in list(A) + list(B))
+    if prefix == PREFIX_MUX:
+        p = [c.gate(XOR, A[i], B[i], base + 1) for i in range(W)]
+        G = [c.gate(OR if (i == 0 and carry_in == 1) else AND, A[i], B[i], base + 1) for i in range(W)]
+        P = list(p)
+        last = base + 2 + _prefix_mux(c, G, P, base + 1)
+        cin = c.const(1 if carry_in == 1 else 0)
+        s = [c.gate(XOR, p[0], cin, last)] + [c.gate(XOR, p[i], G[i - 1], last) for i in range(1, W)]
+        return s, G[W - 1]
+    if prefix != PREFIX_GATES:
+        raise ValueError(f"unknown prefix form {prefix}")
     g = [c.gate(AND, A[i], B[i], base + 1) for i in range(W)]
     p = [c.gate(XOR, A[i], B[i], base + 1) for i in range(W)]
     G = list(g)
@@ -168,10 +211,11 @@ def kogge_stone_add(c: Circuit, A: list, B: list, carry_in: int | None = None):
     return s, G[W - 1]
 
 
-def add_with_carry_wire(c: Circuit, A: list, B: list, cin: int):
+def add_with_carry_wire(c: Circuit, A: list, B: list, cin: int, prefix: str = PREFIX_GATES):
     """Kogge-Stone A + B + cin with an encrypted carry-in wire: the carry is
     prefix position -1 with (G, P) = (cin, 0), so it enters through the same
-    o levels as every other position (ceil(log2(W + 1)) prefix levels).
+    o levels as every other position (ceil(log2(W + 1)) prefix levels, each
+    two gate levels deep, or one with prefix = PREFIX_MUX).
     Returns (sum wires, carry-out wire)."""
     W = len(A)
     base = max(c.lv[w] for w in list(A) + list(B) + [cin])
@@ -179,6 +223,12 @@ def add_with_carry_wire(c: Circuit, A: list, B: list, cin: int):
     p = [c.gate(XOR, A[i], B[i], base + 1) for i in range(W)]
     G = [cin] + g                  # index 0 = position -1
     P = [None] + list(p)           # None = known zero
+    if prefix == PREFIX_MUX:
+        last = base + 2 + _prefix_mux(c, G, P, base + 1)
+        s = [c.gate(XOR, p[i], G[i], last) for i in range(W)]
+        return s, G[W]
+    if prefix != PREFIX_GATES:
+        raise ValueError(f"unknown prefix form {prefix}")
     d, k = 1, 1
     while d < W + 1:
         newG, newP = {}, {}
@@ -196,16 +246,16 @@ def add_with_carry_wire(c: Circuit, A: list, B: list, cin: int):
     return s, G[W]
 
 
-def subtract(c: Circuit, A: list, B: list):
+def subtract(c: Circuit, A: list, B: list, prefix: str = PREFIX_GATES):
     """a - b = a + NOT(b) + 1 (Sec. 5.3). Returns (difference wires, carry-out
     wire; carry-out 1 means no borrow, i.e. a >= b unsigned)."""
     nb = [c.NOT(b) for b in B]
-    return kogge_stone_add(c, A, nb, carry_in=1)
+    return kogge_stone_add(c, A, nb, carry_in=1, prefix=prefix)
 
 
-def less_than(c: Circuit, A: list, B: list) -> int:
+def less_than(c: Circuit, A: list, B: list, prefix: str = PREFIX_GATES) -> int:
     """Unsigned a < b: the borrow of a - b, i.e. NOT(carry-out)."""
-    _, carry = subtract(c, A, B)
+    _, carry = subtract(c, A, B, prefix)
     return c.NOT(carry)
 
 
@@ -233,7 +283,7 @@ def _full_add(c: Circuit, a: int, b: int, cin: int):
     return s, cout
 
 
-def array_multiply(c: Circuit, A: list, B: list) -> list:
+def array_multiply(c: Circuit, A: list, B: list, prefix: str = PREFIX_GATES) -> list:
     """Unsigned W x W -> 2W product as an array multiplier: the W^2 AND partial
     products (one level), rows accumulated in carry-save form with full and
     half adders, and a final Kogge-Stone adder for the sum and carry vectors.
@@ -266,7 +316,7 @@ def array_multiply(c: Circuit, A: list, B: list) -> list:
     zero = c.const(0)
     Sw = [w if w is not None else zero for w in S]
     Cw = [w if w is not None else zero for w in Cv]
-    out, _ = kogge_stone_add(c, Sw, Cw)
+    out, _ = kogge_stone_add(c, Sw, Cw, prefix=prefix)
     return out
 
 
@@ -318,7 +368,7 @@ def shift_immediate(c: Circuit, A: list, amount: int, mode: str) -> list:
     raise ValueError(f"unknown shift mode {mode}")
 
 
-def sequential_multiply(c: Circuit, A: list, B: list, signed: bool = False) -> list:
+def sequential_multiply(c: Circuit, A: list, B: list, signed: bool = False, prefix: str = PREFIX_GATES) -> list:
     """The paper's sequential (carry-save) multiplier (Sec. 5.5): P = 0; W
     times: (P, carry) = P + (B[i] ? A : 0) with a W-bit Kogge-Stone adder,
     then [carry, P, B] >> 1, so bit i of the product is the low sum bit of
@@ -341,7 +391,7 @@ def sequential_multiply(c: Circuit, A: list, B: list, signed: bool = False) -> l
         for j in range(W):
             invert = signed and ((j == W - 1) != last)
             row.append(c.gate(NAND if invert else AND, A[j], B[i]))
-        S, carry = kogge_stone_add(c, P, row, carry_in=1 if (signed and last) else None)
+        S, carry = kogge_stone_add(c, P, row, carry_in=1 if (signed and last) else None, prefix=prefix)
         low.append(S[0])
         P = S[1:] + [carry]
     out = low + P
@@ -350,7 +400,7 @@ def sequential_multiply(c: Circuit, A: list, B: list, signed: bool = False) -> l
     return out
 
 
-def nonrestoring_divide(c: Circuit, Q: list, D: list) -> list:
+def nonrestoring_divide(c: Circuit, Q: list, D: list, prefix: str = PREFIX_GATES) -> list:
     """Unsigned non-restoring division (Sec. 5.6): A = 0 (one bit wider than
     the operands, the sign bit), W times: shift [A, Q] left, then A = A - D
     if A was >= 0 before the shift, else A = A + D, and Q[0] = NOT sign(A).
@@ -366,7 +416,7 @@ def nonrestoring_divide(c: Circuit, Q: list, D: list) -> list:
         A = [Q[W - 1]] + A[:W]
         Q = [None] + Q[:W - 1]
         Dx = [c.gate(XOR, D[j], sub) for j in range(W)] + [sub]   # D's top bit is 0
-        A, _ = add_with_carry_wire(c, A, Dx, sub)
+        A, _ = add_with_carry_wire(c, A, Dx, sub, prefix)
         Q[0] = c.NOT(A[W])
     return Q
 
@@ -404,22 +454,21 @@ def nzcv_flags(c: Circuit, result: list, carry: int | None = None, a_msb: int | 
     return [n_flag, z_flag, c_flag, v_flag]
 
 
-def adder_instance(width: int, carry_in_one: bool = False):
-    """A standalone W-bit ADD (or SUB if carry_in_one and inputs negated by the
-    caller) circuit: inputs a[0..W), b[0..W); output 'sum'."""
+def adder_instance(width: int, prefix: str = PREFIX_GATES):
+    """A standalone W-bit ADD circuit: inputs a[0..W), b[0..W); output 'sum'."""
     c = Circuit()
     A = c.inputs_word(width)
     B = c.inputs_word(width)
-    s, _ = kogge_stone_add(c, A, B)
+    s, _ = kogge_stone_add(c, A, B, prefix=prefix)
     c.outputs["sum"] = s
     return c
 
 
-def sub_instance(width: int):
+def sub_instance(width: int, prefix: str = PREFIX_GATES):
     c = Circuit()
     A = c.inputs_word(width)
     B = c.inputs_word(width)
-    s, _ = subtract(c, A, B)
+    s, _ = subtract(c, A, B, prefix)
     c.outputs["diff"] = s
     return c
 
@@ -525,6 +574,9 @@ class Program:
         self._dev = {
             "levels": [(t(L.ops), t(L.ia), t(L.ib), t(L.io), t(L.nots[0]), t(L.nots[1])) for L in self.levels],
             "mux": [tuple(t(x) for x in L.mux) for L in self.levels],
+            # output rows of a level holding both gates and MUXes: gates first
+            "level_io": [t(np.concatenate([L.io, L.mux[3]])) if L.io.shape[0] and L.num_muxes else None
+                         for L in self.levels],
             "tail": (t(self.tail_nots[0]), t(self.tail_nots[1])),
             "consts": (t(self.consts[0]), t(self.consts[1])),
         }
@@ -532,9 +584,11 @@ class Program:
 
     def run(self, keys, pool, form="fft64", stream=None, profile_levels=None, tuner=None):
         """Enqueue the whole program on `stream`: constants, then per level the
-        NOTs it needs, one batched gate launch and one batched MUX launch
-        (gather/scatter in `pool`). With an autotuner, each launch's form and
-        tiles are the tuner's choice for its number of blind rotations."""
+        NOTs it needs and one batched launch of the level's gates and MUXes
+        (gather/scatter in `pool`; a level holding both goes through
+        cemu_bootstrap_level, so its blind rotations share one launch). With
+        an autotuner, each launch's form and tiles are the tuner's choice for
+        its number of blind rotations."""
         import torch
         if self._dev is None:
             self.to_device(pool.device)
@@ -549,12 +603,15 @@ class Program:
             if profile_levels is not None:
                 ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 ev[0].record(stream)
-            if ops.shape[0]:
-                f = tuner.apply(int(ops.shape[0])) if tuner is not None else form
-                cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=f, stream=stream)
             ms, ma, mb, mo = d["mux"][li]
-            if ms.shape[0]:
-                f = tuner.apply(2 * int(ms.shape[0])) if tuner is not None else form
+            G, M = int(ops.shape[0]), int(ms.shape[0])
+            f = tuner.apply(G + 2 * M) if (tuner is not None and G + M) else form
+            if G and M:
+                cemu.bootstrap_level(keys, pool, (ops, ia, ib), (ms, ma, mb), pool, io=d["level_io"][li], form=f,
+                                     stream=stream)
+            elif G:
+                cemu.bootstrap_gates(keys, ops, pool, ia, ib, pool, io=io, form=f, stream=stream)
+            elif M:
                 cemu.mux(keys, pool, ms, ma, mb, pool, io=mo, form=f, stream=stream)
             if ev is not None:
                 ev[1].record(stream)
@@ -580,7 +637,7 @@ class Program:
         return g
 
 
-def flag_setting_circuit(kind: str, width: int) -> Circuit:
+def flag_setting_circuit(kind: str, width: int, prefix: str = PREFIX_GATES) -> Circuit:
     """ADDS / SUBS (and CMP, which is SUBS without a destination): outputs
     'out' (the W-bit result) and 'nzcv' (the four flags, Sec. 6.1). For
     SUBS, C = 1 means no borrow (a >= b unsigned) and V is taken on the
@@ -589,10 +646,10 @@ def flag_setting_circuit(kind: str, width: int) -> Circuit:
     A = c.inputs_word(width)
     B = c.inputs_word(width)
     if kind == "ADDS":
-        out, carry = kogge_stone_add(c, A, B)
+        out, carry = kogge_stone_add(c, A, B, prefix=prefix)
         b_top = B[width - 1]
     elif kind in ("SUBS", "CMP"):
-        out, carry = subtract(c, A, B)
+        out, carry = subtract(c, A, B, prefix)
         b_top = c.NOT(B[width - 1])
     else:
         raise ValueError(f"unknown flag-setting instruction {kind}")
@@ -614,21 +671,21 @@ def nzcv_reference(kind: str, width: int, a: int, b: int) -> list:
     return [r >> (width - 1), int(r == 0), cflag, vflag]
 
 
-def instruction_circuit(kind: str, width: int) -> Circuit:
+def instruction_circuit(kind: str, width: int, prefix: str = PREFIX_GATES) -> Circuit:
     """One instruction as a circuit with inputs a, b (width bits each, LSB
     first) and output 'out'. Shifts (LLS / LRS / ARS) are register mode: b is
-    the shift-amount register."""
+    the shift-amount register. prefix picks the adders' prefix form."""
     c = Circuit()
     A = c.inputs_word(width)
     B = c.inputs_word(width)
     if kind == "ADD":
-        out, _ = kogge_stone_add(c, A, B)
+        out, _ = kogge_stone_add(c, A, B, prefix=prefix)
     elif kind == "SUB":
-        out, _ = subtract(c, A, B)
+        out, _ = subtract(c, A, B, prefix)
     elif kind == "MUL":
-        out = array_multiply(c, A, B)
+        out = array_multiply(c, A, B, prefix)
     elif kind == "LT":
-        out = [less_than(c, A, B)]
+        out = [less_than(c, A, B, prefix)]
     elif kind == "EQ":
         out = [equal(c, A, B)]
     elif kind in ("AND", "OR", "XOR"):
@@ -636,11 +693,11 @@ def instruction_circuit(kind: str, width: int) -> Circuit:
     elif kind in (LLS, LRS, ARS):
         out = barrel_shift(c, A, B, kind)
     elif kind == "MULSEQ":
-        out = sequential_multiply(c, A, B, signed=False)
+        out = sequential_multiply(c, A, B, signed=False, prefix=prefix)
     elif kind == "SMULSEQ":
-        out = sequential_multiply(c, A, B, signed=True)
+        out = sequential_multiply(c, A, B, signed=True, prefix=prefix)
     elif kind == "DIV":
-        out = nonrestoring_divide(c, A, B)
+        out = nonrestoring_divide(c, A, B, prefix)
     elif kind == "ORN":
         out = bitwise(c, ORYN, A, B)
     else:

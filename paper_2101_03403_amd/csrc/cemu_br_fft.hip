@@ -8,10 +8,12 @@
 //   z_j = (P_j + i P_{j+N/2}) w^j  ->  FFT_{N/2}  ->  pointwise products
 //   ->  inverse FFT / (N/2)  ->  times w^{-j}  ->  (R_j, R_{j+N/2}) = (Re, Im).
 // The key polynomials are taken as centred int32 values and their spectra
-// are precomputed once per key; digits are small integers. Sums reach about
-// 2^50 in magnitude, so the final rounding to integers can be off by a few
-// units in the last place of the torus: this form is approximate, unlike the
-// int8 form, and its deviation is measured against the oracle.
+// are precomputed once per key; digits are small integers. Every product is
+// an integer polynomial, so the double result rounds to the exact integer as
+// long as the transform error stays below 1/2. Sums stay near 2^42 for the
+// random key coefficients (3 * 2^50 is the adversarial bound), where the
+// error is far below 1/2; but the form is not exact by construction, unlike
+// the int8 form, and its deviation is measured against the oracle.
 //
 // FFT of 512 points per wave: lane l holds x[l + 64 m], m = 0..7. Three
 // radix-8 passes (512 = 8^3, decimation in frequency) with two LDS

@@ -1,7 +1,8 @@
 // Device part of libcemu for gfx950 (MI355X): key upload, the gate
 // linear-combination + modulus-switch kernel, the two halves of the
 // homomorphic MUX (its lincomb over 2B gates and the combine of the two
-// extracted samples), the blind-rotation kernels (int8-MFMA form in
+// extracted samples), circuit levels that mix gates and MUXes in one
+// blind-rotation launch, the blind-rotation kernels (int8-MFMA form in
 // cemu_br_int8.hip, FFT64 form in cemu_br_fft.hip), the key-switching
 // kernels (MFMA form in cemu_ks.hip, VALU form here), the unbootstrapped
 // NOT / COPY / CONSTANT kernels, and the device entry points of the C ABI.
@@ -250,7 +251,7 @@ int log2_of(int v)
 }
 
 int launch_lincomb(const cemu_cloud_key *ck, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
-                   const int32_t *ib, int64_t B, hipStream_t s)
+                   const int32_t *ib, int64_t B, uint16_t *bars, hipStream_t s)
 {
     const int32_t n = ck->p.n;
     const int64_t total = B * (n + 1);
@@ -258,7 +259,7 @@ int launch_lincomb(const cemu_cloud_key *ck, const uint8_t *ops, const uint32_t 
     const int64_t blocks = (total + threads - 1) / threads;
     void *ev = prof_begin(ck, s);
     hipLaunchKernelGGL(lincomb_modswitch_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, ops, pool, ia, ib, n,
-                       log2_of(2 * ck->p.N), B, ck->d_bars);
+                       log2_of(2 * ck->p.N), B, bars);
     CEMU_HIP(hipGetLastError());
     prof_end(ck, 0, s, ev);
     return CEMU_OK;
@@ -313,32 +314,40 @@ int run_br(cemu_cloud_key *ck, int form, uint32_t *ext_out, int64_t B, hipStream
 int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
                      const int32_t *ib, uint32_t *ext_out, int64_t B, hipStream_t s)
 {
-    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, s);
+    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, ck->d_bars, s);
     if (rc) return rc;
     return run_br(ck, form, ext_out, B, s);
 }
 
-int run_mux(cemu_cloud_key *ck, int form, const uint32_t *pool, const int32_t *is, const int32_t *ia,
-            const int32_t *ib, const int32_t *io, uint32_t *pool_out, int64_t B, hipStream_t s)
+// G gates and M multiplexers through one blind-rotation launch and one key
+// switch. Workspace rows: [0, G) the gates, [G, G + M) the AND(s, a) halves
+// and [G + M, G + 2M) the ANDNY(s, b) halves of the multiplexers; after the
+// combine, rows [0, G + M) are the samples to key-switch, in output order.
+int run_level(cemu_cloud_key *ck, int form, const uint32_t *pool, const uint8_t *ops, const int32_t *ia,
+              const int32_t *ib, int64_t G, const int32_t *ms, const int32_t *ma, const int32_t *mb, int64_t M,
+              const int32_t *io, uint32_t *pool_out, hipStream_t s)
 {
     const int32_t n = ck->p.n, N = ck->p.N;
     const int threads = 256;
-    {
-        const int64_t blocks = (2 * B * (n + 1) + threads - 1) / threads;
+    int rc;
+    if (G > 0 && (rc = launch_lincomb(ck, ops, pool, ia, ib, G, ck->d_bars, s))) return rc;
+    if (M > 0) {
+        const int64_t blocks = (2 * M * (n + 1) + threads - 1) / threads;
         void *ev = prof_begin(ck, s);
-        hipLaunchKernelGGL(mux_lincomb_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, pool, is, ia, ib, n,
-                           log2_of(2 * N), B, ck->d_bars);
+        hipLaunchKernelGGL(mux_lincomb_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, pool, ms, ma, mb, n,
+                           log2_of(2 * N), M, ck->d_bars + G * (n + 1));
         CEMU_HIP(hipGetLastError());
         prof_end(ck, 0, s, ev);
     }
-    int rc = run_br(ck, form, ck->d_ext, 2 * B, s);
+    rc = run_br(ck, form, ck->d_ext, G + 2 * M, s);
     if (rc) return rc;
-    {
-        const int64_t blocks = (B * (N + 1) + threads - 1) / threads;
-        hipLaunchKernelGGL(mux_combine_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, ck->d_ext, N, B);
+    if (M > 0) {
+        const int64_t blocks = (M * (N + 1) + threads - 1) / threads;
+        hipLaunchKernelGGL(mux_combine_kernel, dim3((unsigned)blocks), dim3(threads), 0, s,
+                           ck->d_ext + G * (N + 1), N, M);
         CEMU_HIP(hipGetLastError());
     }
-    return launch_key_switch(ck, ck->d_ext, io, pool_out, B, s);
+    return launch_key_switch(ck, ck->d_ext, io, pool_out, G + M, s);
 }
 
 }  // namespace
@@ -473,7 +482,32 @@ int cemu_mux(const cemu_cloud_key *ckc, int form, const uint32_t *pool_in, const
     if (rc) return rc;
     rc = ensure_workspace(ck, 2 * B, true);
     if (rc) return rc;
-    return run_mux(ck, form, pool_in, is, ia, ib, io, pool_out, B, (hipStream_t)hip_stream);
+    return run_level(ck, form, pool_in, nullptr, nullptr, nullptr, 0, is, ia, ib, B, io, pool_out,
+                     (hipStream_t)hip_stream);
+}
+
+int cemu_bootstrap_level(const cemu_cloud_key *ckc, int form, const uint32_t *pool_in, const uint8_t *ops,
+                         const int32_t *ia, const int32_t *ib, int64_t G, const int32_t *ms, const int32_t *ma,
+                         const int32_t *mb, int64_t M, const int32_t *io, uint32_t *pool_out, void *hip_stream)
+{
+    clear_error();
+    if (!ckc) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    if (G < 0 || M < 0) return fail(CEMU_ERR_RANGE, "G < 0 or M < 0");
+    if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
+    if (G == 0 && M == 0) return CEMU_OK;
+    if (G > ((int64_t)1 << 40) || M > ((int64_t)1 << 40)) return fail(CEMU_ERR_RANGE, "batch too large");
+    if (!pool_in || !pool_out || (G > 0 && (!ops || !ia || !ib)) || (M > 0 && (!ms || !ma || !mb)))
+        return fail(CEMU_ERR_NULL, "NULL device buffer");
+    if (misaligned(pool_in) || misaligned(pool_out) || (io && misaligned(io)) ||
+        (G > 0 && (misaligned(ia) || misaligned(ib))) || (M > 0 && (misaligned(ms) || misaligned(ma) || misaligned(mb))))
+        return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    cemu_cloud_key *ck = const_cast<cemu_cloud_key *>(ckc);
+    std::lock_guard<std::mutex> lock(ck->mu);
+    int rc = check_device(ck);
+    if (rc) return rc;
+    rc = ensure_workspace(ck, G + 2 * M, true);
+    if (rc) return rc;
+    return run_level(ck, form, pool_in, ops, ia, ib, G, ms, ma, mb, M, io, pool_out, (hipStream_t)hip_stream);
 }
 
 int cemu_blind_rotate_extract(const cemu_cloud_key *ckc, int form, const uint8_t *ops, const uint32_t *pool_in,

@@ -175,12 +175,14 @@ class Machine:
     [mem_words][W] as ciphertext pools, NZCV as a 4-row pool, a cleartext PC.
 
     form / tuner: the product form and the autotuner (or ``None`` for the
-    form with the cloud key's current launch shape) used by every level."""
+    form with the cloud key's current launch shape) used by every level.
+    prefix: the adders' prefix form (circuits.PREFIX_GATES, the paper's, or
+    circuits.PREFIX_MUX, fewer levels)."""
 
     def __init__(self, keys: cemu.Keys, width: int = 32, nregs: int = 16, mem_words: int = 0, form: str = "fft64",
-                 tuner=None, device=None):
+                 tuner=None, device=None, prefix: str = C.PREFIX_GATES):
         import torch
-        self.keys, self.W, self.form, self.tuner = keys, width, form, tuner
+        self.keys, self.W, self.form, self.tuner, self.prefix = keys, width, form, tuner, prefix
         self.device = device if device is not None else torch.device("cuda", torch.cuda.current_device())
         n1 = keys.n + 1
         self.regs = torch.zeros((nregs * width, n1), dtype=torch.int32, device=self.device)
@@ -226,14 +228,14 @@ class Machine:
         key = (kind, imm_shift)
         if key not in self._units:
             if kind in FLAG_KINDS.values():
-                circ = C.flag_setting_circuit(kind, self.W)
+                circ = C.flag_setting_circuit(kind, self.W, self.prefix)
             elif imm_shift is not None:
                 circ = C.Circuit()
                 A = circ.inputs_word(self.W)
                 circ.inputs_word(self.W)               # unused second operand keeps the layout uniform
                 circ.outputs["out"] = C.shift_immediate(circ, A, imm_shift, kind)
             else:
-                circ = C.instruction_circuit(kind, self.W)
+                circ = C.instruction_circuit(kind, self.W, self.prefix)
             self._units[key] = _Unit(circ, self.keys, self.device)
         return self._units[key]
 

@@ -253,3 +253,87 @@ def test_sequential_units_under_fhe_with_oracle():
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
         assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
 
+
+
+# ------------------------------------------------------------------ MUX form of the prefix stage
+MUX_KINDS = ["ADD", "SUB", "LT", "MUL", "MULSEQ", "SMULSEQ", "DIV"]
+
+
+@pytest.mark.parametrize("width", [1, 2, 3, 4, 5])
+def test_mux_prefix_units_exhaustive(width):
+    """Every adder-based unit with the MUX prefix form, all operand pairs."""
+    cs = {k: C.instruction_circuit(k, width, prefix=C.PREFIX_MUX) for k in MUX_KINDS}
+    fl = {k: C.flag_setting_circuit(k, width, prefix=C.PREFIX_MUX) for k in ("ADDS", "SUBS")}
+    for a in range(1 << width):
+        for b in range(1 << width):
+            bits = C.int_to_bits(a, width) + C.int_to_bits(b, width)
+            for k, c in cs.items():
+                v = c.eval_plain(bits)
+                assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(k, width, a, b), (k, a, b)
+            for k, c in fl.items():
+                v = c.eval_plain(bits)
+                assert [int(x) for x in v[c.outputs["nzcv"]]] == C.nzcv_reference(k, width, a, b), (k, a, b)
+
+
+@pytest.mark.parametrize("kind", ["ADD", "SUB", "LT", "MULSEQ", "DIV"])
+def test_mux_prefix_units_cleartext_32(kind):
+    rng = np.random.default_rng(len(kind) * 13)
+    c = C.instruction_circuit(kind, 32, prefix=C.PREFIX_MUX)
+    m = (1 << 32) - 1
+    cases = [(m, m), (0, 0), (m, 1), (1 << 31, 1 << 31), (5, 0)]
+    cases += [tuple(int(x) for x in rng.integers(0, 1 << 32, 2, dtype=np.uint64)) for _ in range(25)]
+    for a, b in cases:
+        v = c.eval_plain(C.int_to_bits(a, 32) + C.int_to_bits(b, 32))
+        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, 32, a, b), (a, b)
+
+
+def test_mux_prefix_structure_32():
+    """One MUX per o: the MUX counts per prefix level are the paper's o counts
+    (31, 30, 28, 24, 16), the propagate ANDs are only those a later level
+    reads (positions >= 2d), and the adder is log2 W + 2 = 7 levels deep."""
+    for kind in ("ADD", "SUB"):
+        p = C.Program([C.instruction_circuit(kind, 32, prefix=C.PREFIX_MUX)])
+        assert p.depth == 7
+        assert p.level_mux_counts() == [0, 31, 30, 28, 24, 16, 0]
+        assert p.level_widths() == [64, 30, 28, 24, 16, 0, 32]
+        assert p.num_bootstraps() == 64 + 2 * 129 + 98 + 32
+    p16 = C.Program([C.adder_instance(16, prefix=C.PREFIX_MUX)])
+    assert p16.depth == 6 and p16.level_mux_counts()[1:5] == [15, 14, 12, 8]
+    for w, mul_depth, div_depth in [(8, 41, 56), (32, 225, 288)]:
+        assert C.instruction_circuit("MULSEQ", w, prefix=C.PREFIX_MUX).depth() == mul_depth
+        assert C.instruction_circuit("DIV", w, prefix=C.PREFIX_MUX).depth() == div_depth
+    with pytest.raises(ValueError):
+        C.adder_instance(8, prefix="tree")
+
+
+def test_mux_prefix_add_with_carry_wire_cleartext():
+    for w in (1, 3, 8, 17):
+        c = C.Circuit()
+        A, B = c.inputs_word(w), c.inputs_word(w)
+        cin = c.input()
+        s, cout = C.add_with_carry_wire(c, A, B, cin, C.PREFIX_MUX)
+        rng = np.random.default_rng(w + 100)
+        for _ in range(40):
+            a, b, ci = int(rng.integers(0, 1 << w)), int(rng.integers(0, 1 << w)), int(rng.integers(0, 2))
+            v = c.eval_plain(C.int_to_bits(a, w) + C.int_to_bits(b, w) + [ci])
+            assert C.bits_to_int(v[s]) + (int(v[cout]) << w) == a + b + ci
+
+
+def test_mux_prefix_under_fhe_with_oracle():
+    """8-bit ADD and SUB and a 4-bit DIV with the MUX prefix form, evaluated
+    with the oracle's gates and MUX (toy parameters, levels that mix both),
+    then decrypted."""
+    from oracle import oracle as O
+    okeys = O.keygen(O.TOY, 96)
+    cases = [("ADD", 8, 201, 99), ("SUB", 8, 17, 50), ("DIV", 4, 13, 4)]
+    cs = [C.instruction_circuit(k, w, prefix=C.PREFIX_MUX) for k, w, _, _ in cases]
+    prog = C.Program(cs)
+    assert any(L.ops.shape[0] and L.num_muxes for L in prog.levels)
+    bits = []
+    for k, w, a, b in cases:
+        bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
+    pool = _run_with_oracle(prog, okeys, bits, enc_seed=10)
+    for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
+        rows = np.array(c.outputs["out"]) + off
+        got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
+        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)

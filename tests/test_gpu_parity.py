@@ -550,3 +550,111 @@ def test_program_sequential_multiplier_and_divider(std, dev):
                                     want_extracted=False)
         assert np.array_equal(host[L.io[pick]], oout)
 
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+@pytest.mark.parametrize("form", ["int8", "fft64"])
+def test_bootstrap_level_matches_separate_calls(std, dev, form):
+    """A level of G gates and M MUXes through cemu_bootstrap_level (one
+    blind-rotation launch of G + 2M) equals, word for word, cemu_bootstrap_gates
+    plus cemu_mux on the same inputs; outputs scattered to permuted distinct
+    rows; pure-gate and pure-MUX levels too; decryptions exact; int8 sampled
+    gates and MUXes bit-exact against the oracle."""
+    from paper_2101_03403_amd import circuits as Cc
+    lk, ok = std
+    rng = np.random.default_rng(91)
+    R, G, M = 40, 29, 13
+    say(f"[gpu] bootstrap_level {form} G={G} M={M}")
+    bits = rng.integers(0, 2, R).astype(np.uint8)
+    host_in = lk.encrypt(bits, seed=W.ENC_SEED + 40)
+    pool = to_dev(host_in, dev)
+    ops_h = rng.integers(0, 10, G).astype(np.uint8)
+    ia_h, ib_h = (rng.integers(0, R, G).astype(np.int32) for _ in range(2))
+    ms_h, ma_h, mb_h = (rng.integers(0, R, M).astype(np.int32) for _ in range(3))
+    perm = rng.permutation(G + M + 7)[:G + M].astype(np.int32)
+    ops, ia, ib, ms, ma, mb, io = (_t(x, dev) for x in (ops_h, ia_h, ib_h, ms_h, ma_h, mb_h, perm))
+    out_level = torch.zeros((G + M + 7, lk.n + 1), dtype=torch.int32, device=dev)
+    out_sep = torch.zeros_like(out_level)
+    cemu.bootstrap_level(lk, pool, (ops, ia, ib), (ms, ma, mb), out_level, io=io, form=form)
+    cemu.bootstrap_gates(lk, ops, pool, ia, ib, out_sep, io=_t(perm[:G], dev), form=form)
+    cemu.mux(lk, pool, ms, ma, mb, out_sep, io=_t(perm[G:], dev), form=form)
+    only_g = torch.zeros((G, lk.n + 1), dtype=torch.int32, device=dev)
+    only_g_ref = torch.zeros_like(only_g)
+    cemu.bootstrap_level(lk, pool, (ops, ia, ib), None, only_g, form=form)
+    cemu.bootstrap_gates(lk, ops, pool, ia, ib, only_g_ref, form=form)
+    only_m = torch.zeros((M, lk.n + 1), dtype=torch.int32, device=dev)
+    only_m_ref = torch.zeros_like(only_m)
+    cemu.bootstrap_level(lk, pool, None, (ms, ma, mb), only_m, form=form)
+    cemu.mux(lk, pool, ms, ma, mb, only_m_ref, form=form)
+    cemu.bootstrap_level(lk, pool, None, None, only_m, form=form)     # G = M = 0: no-op
+    torch.cuda.synchronize()
+    assert torch.equal(out_level, out_sep)
+    assert torch.equal(only_g, only_g_ref) and torch.equal(only_m, only_m_ref)
+    host = to_host_u32(out_level)
+    want_g = np.array([Cc._PLAIN[int(o)](int(bits[a]), int(bits[b])) for o, a, b in zip(ops_h, ia_h, ib_h)])
+    want_m = np.where(bits[ms_h] == 1, bits[ma_h], bits[mb_h])
+    assert np.array_equal(lk.decrypt(host[perm[:G]]), want_g)
+    assert np.array_equal(lk.decrypt(host[perm[G:]]), want_m)
+    if form == "int8":
+        pg, pm = W.sample_indices(G, 3, seed=2), W.sample_indices(M, 3, seed=3)
+        _, og = O.bootstrap_batch(ok, ops_h[pg].astype(np.int32), host_in[ia_h[pg]], host_in[ib_h[pg]],
+                                  want_extracted=False)
+        assert np.array_equal(host[perm[pg]], og)
+        om = O.mux_batch(ok, host_in[ms_h[pm]], host_in[ma_h[pm]], host_in[mb_h[pm]])
+        assert np.array_equal(host[perm[G + pm]], om)
+    p = C.c_void_p(pool.data_ptr())
+    lib = cemu.lib()
+    assert lib.cemu_bootstrap_level(lk.ck, 0, p, p, p, p, -1, None, None, None, 0, None, p, None) == -8
+    assert lib.cemu_bootstrap_level(lk.ck, 7, p, p, p, p, 1, None, None, None, 0, None, p, None) != 0
+    assert lib.cemu_bootstrap_level(lk.ck, 0, p, p, p, p, 0, None, None, None, 2, None, p, None) != 0
+
+
+def test_program_mux_prefix_levels_and_graph(std, dev):
+    """ADD32, SUB32 and LT32 with the MUX prefix form (7 levels, gates and
+    MUXes sharing launches), merged across instances, int8 form: decryptions
+    equal uint32 arithmetic; on every level 2 sampled gates and 2 sampled
+    MUXes are bit-exact against the oracle on the GPU's own level inputs; a
+    captured hipGraph replays the run exactly."""
+    from paper_2101_03403_amd import circuits as Cc
+    lk, ok = std
+    rng = np.random.default_rng(321)
+    cases = [(k, 32) + tuple(int(x) for x in rng.integers(0, 1 << 32, 2, dtype=np.uint64))
+             for k in ("ADD",) * 5 + ("SUB",) * 5 + ("LT",) * 3]
+    cs = [Cc.instruction_circuit(k, w, prefix=Cc.PREFIX_MUX) for k, w, _, _ in cases]
+    prog = Cc.Program(cs).to_device(dev)
+    assert prog.depth == 7
+    bits = []
+    for k, w, a, b in cases:
+        bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
+    say(f"[gpu] mux-prefix program: {prog.num_bootstraps()} blind rotations in {prog.depth} levels")
+    pool = _program_pool(prog, lk, bits, dev)
+    prog.run(lk, pool, form="int8")
+    torch.cuda.synchronize()
+    host = to_host_u32(pool)
+    for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
+        got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
+        assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
+    rs = np.random.default_rng(9)
+    for L in prog.levels:
+        if L.ops.shape[0]:
+            pick = rs.choice(L.ops.shape[0], 2, replace=False)
+            _, oout = O.bootstrap_batch(ok, L.ops[pick].astype(np.int32), host[L.ia[pick]], host[L.ib[pick]],
+                                        want_extracted=False)
+            assert np.array_equal(host[L.io[pick]], oout)
+        if L.num_muxes:
+            ms, ma, mb, mo = L.mux
+            pick = rs.choice(ms.shape[0], 2, replace=False)
+            assert np.array_equal(host[mo[pick]], O.mux_batch(ok, host[ms[pick]], host[ma[pick]], host[mb[pick]]))
+    eager = host.copy()
+    g = prog.capture(lk, pool, form="int8")
+    keep = torch.zeros(prog.rows, dtype=torch.bool, device=dev)
+    keep[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = True
+    for rep in range(2):
+        pool[~keep] = 0
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host_u32(pool), eager), f"graph replay {rep} differs"

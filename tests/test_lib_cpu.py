@@ -54,6 +54,7 @@ def test_null_and_range_errors():
     assert L.cemu_params_default(None, 0) == -2
     assert L.cemu_bootstrap_gates(None, 0, None, None, None, None, None, None, 4, None) == -2
     assert L.cemu_key_switch(None, None, None, 1, None) == -2
+    assert L.cemu_bootstrap_level(None, 0, None, None, None, None, 1, None, None, None, 1, None, None, None) == -2
     assert L.cemu_lwe_not(630, None, None, None, None, -1, None) == -8
     assert L.cemu_lwe_not(630, None, None, None, None, 0, None) == 0
     assert L.cemu_encrypt(None, None, 0, 0, 0, None) == -2
