@@ -41,20 +41,31 @@ FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
 # HBM bytes per launch of the blind-rotation kernels at B = 4096, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, scales from a
 # plain 1 GiB copy); summary and commands in profiles/. Valid only while the
-# kernel source is the one profiled (sha256 prefix), else reported as null.
+# kernel source's code is the one profiled (sha256 prefix of the source with
+# comments and whitespace removed, so that comment edits keep it), else
+# reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "99c9480f5662fd75",
-              "bytes": 487_047 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
-    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "65afeedf9381a23e",
-             "bytes": 245_914 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "51dc2af23be70747",
+              "bytes": 487_055 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "dfef580e980366c5",
+             "bytes": 245_912 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
 }
 
 
-def traffic_bytes(form, B):
+def code_hash(path):
+    """sha256 prefix of a C/C++/HIP source with comments and whitespace removed."""
     import hashlib
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
+
+
+def traffic_bytes(form, B):
     t = TRAFFIC[form]
     try:
-        h = hashlib.sha256(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()[:16]
+        h = code_hash(os.path.join(ROOT, t["source"]))
     except OSError:
         return None
     return t["bytes"] if (h == t["sha256_16"] and B == t["batch"]) else None

@@ -58,6 +58,11 @@ constexpr int FN = 1024;          // ring degree handled by this kernel
 constexpr int FH = FN / 2;        // complex FFT length
 constexpr int SCR = 8 * 72;       // transpose scratch entries per wave (8 blocks of 64 + pad 8)
 constexpr uint32_t kDigitOffset = 0x81020400u;   // see cemu_br_int8.hip
+// Top bit of each 7-bit digit field (bits 31, 24, 17). With the offset added,
+// a field holds d + 64 for the signed digit d in [-64, 64); flipping its top
+// bit leaves d in 7-bit two's complement, so a signed bit-field extract
+// yields d itself.
+constexpr uint32_t kDigitSignBits = 0x81020000u;
 
 __device__ __forceinline__ d2 cmul(d2 a, d2 b) { return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ d2 cconj(d2 a) { return d2{a.x, -a.y}; }
@@ -254,6 +259,17 @@ __device__ __forceinline__ d2 twist_slot(int m)
     return d2{c[m], c[(8 - m) & 7] * (m ? 1.0 : 0.0)};
 }
 
+// Signed 7-bit field of x at bit offset off (wave-uniform), sign-extended:
+// one v_bfe_i32. Written as a VALU instruction because the compiler's own
+// signed bit-field-extract builtin was followed by an unsigned conversion to
+// double here (the sign was lost).
+__device__ __forceinline__ int32_t sbfe7(uint32_t x, uint32_t off)
+{
+    int32_t r;
+    asm("v_bfe_i32 %0, %1, %2, 7" : "=v"(r) : "v"(x), "s"(off));
+    return r;
+}
+
 // Key spectrum preparation: one wave per (step i, digit row r, component q).
 // Reads the int8-limb key (R[u] = limb(E[2N-1-u]), BK[m] at u = N-1-m),
 // centres each Torus32 coefficient, folds, twists and transforms.
@@ -331,7 +347,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
         });
 #pragma unroll 1
         for (int c = 0; c < 2; ++c) {
-            // D = X^a ACC_c - ACC_c at this lane's 16 coefficients (+ digit offset)
+            // D = X^a ACC_c - ACC_c at this lane's 16 coefficients (+ digit offset, field top bits flipped)
             uint32_t dlo[8], dhi[8];
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
@@ -341,7 +357,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
                     const uint32_t tt = (j - a) & (uint32_t)(2 * FN - 1);
                     uint32_t v = acc[c][tt & (uint32_t)(FN - 1)];
                     v = (tt & (uint32_t)FN) ? 0u - v : v;
-                    const uint32_t d = v - acc[c][j] + kDigitOffset;
+                    const uint32_t d = (v - acc[c][j] + kDigitOffset) ^ kDigitSignBits;
                     if (h == 0) dlo[m] = d; else dhi[m] = d;
                 }
             });
@@ -366,8 +382,8 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
                 d2 x[8];
                 static_for<0, 8>([&](auto mI) {
                     constexpr int m = decltype(mI)::value;
-                    const double lo = (double)((int32_t)((dlo[m] >> sh) & 127u) - 64);
-                    const double hi = (double)((int32_t)((dhi[m] >> sh) & 127u) - 64);
+                    const double lo = (double)sbfe7(dlo[m], sh);
+                    const double hi = (double)sbfe7(dhi[m], sh);
                     x[m] = cmul(d2{lo, hi}, twist_slot(m));
                 });
                 __builtin_amdgcn_sched_barrier(0);
