@@ -306,7 +306,7 @@ def emulator_while_loop(keys, dev, form, count=42, tuner=None, prefix="gates"):
             "form": form if tuner is None else "autotuned per level width"}
 
 
-def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
+def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None, prefix="gates"):
     """1024 independent instructions (40 % ADD/SUB, 20 % 8x8/16x16 array MUL,
     20 % LT/EQ, 20 % AND/OR/XOR; widths 8/16/32), gates of each level merged
     across instructions into one launch. Makespan of one warm run."""
@@ -314,7 +314,7 @@ def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
     from paper_2101_03403_amd import circuits as Cc, workloads as W
 
     mix = W.instruction_mix(count, seed)
-    cs = [Cc.instruction_circuit(k, w) for k, w, _, _ in mix]
+    cs = [Cc.instruction_circuit(k, w, prefix=prefix) for k, w, _, _ in mix]
     prog = Cc.Program(cs).to_device(dev)
     bits = []
     for k, w, a, b in mix:
@@ -338,9 +338,12 @@ def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None):
     widths = np.array(prog.level_widths())
     hist = {f"<{lim}": int(np.sum(widths < lim)) for lim in (256, 1024, 4096, 16384)}
     hist[">=16384"] = int(np.sum(widths >= 16384))
-    return {"instructions": count, "makespan_ms": ms, "gates": prog.num_gates(), "levels": prog.depth,
-            "gates_per_s": prog.num_gates() / (ms * 1e-3), "decrypt_exact": f"{ok}/{count}",
-            "level_width_histogram": hist, "form": form if tuner is None else "autotuned per level width"}
+    return {"instructions": count, "makespan_ms": ms, "gates": prog.num_gates(), "muxes": prog.num_muxes(),
+            "bootstraps": prog.num_bootstraps(), "levels": prog.depth,
+            "bootstraps_per_s": prog.num_bootstraps() / (ms * 1e-3), "decrypt_exact": f"{ok}/{count}",
+            "level_width_histogram": hist,
+            "prefix": {"gates": "the paper's AND/OR o operator", "mux": "one MUX per o carry"}[prefix],
+            "form": form if tuner is None else "autotuned per level width"}
 
 
 FFT_KERNEL = {8: "br_fft_kernel<8>", 4: "br_fft_kernel<4>", 1: "br_fft_lat_kernel"}
@@ -438,6 +441,7 @@ def main():
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_add_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux")
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
+    rec_mix_mux = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner, prefix="mux")
     rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
     rec_seq = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner)
     rec_seq_mux = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner, prefix="mux")
@@ -466,6 +470,7 @@ def main():
         rec["add32_mux_prefix"] = rec_add_mux
     if rec_mix is not None:
         rec["mixed_stream"] = rec_mix
+        rec["mixed_stream_mux_prefix"] = rec_mix_mux
     if rec_shift is not None:
         rec["shift32"] = rec_shift
     if rec_seq is not None:

@@ -47,7 +47,7 @@ typedef enum cemu_status {
     CEMU_ERR_OOM = -4,          /* host or device allocation failed             */
     CEMU_ERR_HIP = -5,          /* HIP runtime error                            */
     CEMU_ERR_UNSUPPORTED = -6,  /* parameter set the kernels cannot run         */
-    CEMU_ERR_OP = -7,           /* unknown gate op code in a batch (host check) */
+    CEMU_ERR_OP = -7,           /* reserved: op codes are not checked on the device */
     CEMU_ERR_RANGE = -8         /* index or size out of range                   */
 } cemu_status;
 

@@ -10,7 +10,11 @@ Circuits (built from bootstrapped binary gates plus the free NOT / CONSTANT):
     sums s_i = p_i XOR G_{i-1} with G_{-1} = carry-in. For W = 32 the levels
     hold [64 | 62, 31 | 60, 30 | 56, 28 | 48, 24 | 32, 16 | 32] gates
     (o counts 31, 30, 28, 24, 16 as in the text of Sec. 5.2), 483 in total,
-    depth 2 log2 W + 2 = 12.
+    depth 2 log2 W + 2 = 12. With ``prefix=PREFIX_MUX`` the carry half of
+    every o is one FHE MUX (P_x ? G_y : G_x, exact because a position never
+    both generates and propagates), so a prefix level is one level and the
+    32-bit adder is 7 levels deep (452 bootstraps); every adder-based unit
+    below takes the same option.
   * ``subtract`` -- a + NOT(b) + 1 (Sec. 5.3): unbootstrapped NOT of b, the
     carry-in folded into bit 0 by one OR, and the sum bit 0 by one XOR with a
     constant (the subtractor's two extra bootstrapped gates).
@@ -29,10 +33,10 @@ Circuits (built from bootstrapped binary gates plus the free NOT / CONSTANT):
 
 Execution: ``Program`` takes any number of circuit instances, assigns each
 bootstrapped gate to a level (one more than its latest bootstrapped input,
-i.e. the paper's stage order), and merges the gates of one level across all
-instances into a single batched launch (gather from / scatter to one device
-ciphertext pool). The launch sequence can be captured once as a hipGraph and
-replayed.
+i.e. the paper's stage order), and merges the gates and MUXes of one level
+across all instances into a single batched launch (gather from / scatter to
+one device ciphertext pool). The launch sequence can be captured once as a
+hipGraph and replayed.
 """
 from __future__ import annotations
 
