@@ -361,6 +361,32 @@ def output_noise(keys, out, want):
             "margin": 0.125}
 
 
+def noise_chain(keys, form, out1, want1, seed=3):
+    """Second level of a two-level chain: B gates (NAND/AND/OR/XOR) whose
+    inputs are the first level's bootstrapped outputs, in two random
+    permutations. Bootstrapping resets the noise, so the second level's output
+    noise equals the first level's, whatever the (larger, key-switched) input
+    noise was. Returns the second level's output noise and decryptions."""
+    import torch
+    from paper_2101_03403_amd import cemu, workloads as W
+
+    B = out1.shape[0]
+    dev = out1.device
+    rng = np.random.default_rng(seed)
+    ops2, _, _ = W.gate_batch(B, seed=seed + 100)
+    pa, pb = rng.permutation(B).astype(np.int32), rng.permutation(B).astype(np.int32)
+    out2 = torch.zeros_like(out1)
+    cemu.bootstrap_gates(keys, torch.from_numpy(ops2).to(dev), out1, torch.from_numpy(pa).to(dev),
+                         torch.from_numpy(pb).to(dev), out2, form=form)
+    torch.cuda.synchronize()
+    truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
+    want2 = np.array([truth[int(o)](int(want1[a]), int(want1[b])) for o, a, b in zip(ops2, pa, pb)], np.uint8)
+    host2 = out2.cpu().numpy().view(np.uint32)
+    return {"decrypt_exact": f"{int(np.sum(keys.decrypt(host2) == want2))}/{B}",
+            "output_noise": output_noise(keys, host2, want2),
+            "inputs": "the first level's outputs (key-switched, not fresh), two random permutations"}
+
+
 def roofline(form, prof, B, fft_gates_per_wg=8):
     if form == "int8":
         ms, cnt = prof["blind_rotate_int8"]
@@ -417,11 +443,13 @@ def main():
     forms = [args.form] + [f for f in ("fft64", "int8") if f != args.form and not args.only]
     res = {}
     outs = {}
+    dev_outs = {}
     for form in forms:
         out = torch.zeros((B, keys.n + 1), dtype=torch.int32, device=dev)
         wall, prof = run_form(keys, form, ops_t, pool, ia, ib, out, stream, args.steps, args.warmup)
         host = out.cpu().numpy().view(np.uint32)
         outs[form] = host
+        dev_outs[form] = out
         res[form] = {
             "value": B / (wall / args.steps), "ms_per_step": wall * 1e3 / args.steps,
             "roofline": roofline(form, prof, B, args.fft_gates_per_wg),
@@ -430,6 +458,7 @@ def main():
             "output_noise": output_noise(keys, host, want),
         }
     primary = res[args.form]
+    primary["noise_chain_level2"] = noise_chain(keys, args.form, dev_outs[args.form], want)
     if len(outs) == 2:
         same = int(np.sum(np.all(outs["fft64"] == outs["int8"], axis=1)))
         primary["identical_outputs_fft64_vs_int8"] = f"{same}/{B}"
@@ -463,6 +492,7 @@ def main():
                    "form": args.form, "batch": B, "parallelism": "single GPU"},
         "roofline": primary["roofline"], "cpu_baseline": cpu,
         "kernels": primary["kernels"], "decrypt_exact": primary["decrypt_exact"],
+        "output_noise": primary["output_noise"], "noise_chain_level2": primary["noise_chain_level2"],
         "forms": {f: {k: v for k, v in r.items() if k != "kernels"} for f, r in res.items()},
     }
     if rec_add is not None:

@@ -590,8 +590,11 @@ def test_bootstrap_level_matches_separate_calls(std, dev, form):
     cemu.bootstrap_level(lk, pool, None, (ms, ma, mb), only_m, form=form)
     cemu.mux(lk, pool, ms, ma, mb, only_m_ref, form=form)
     cemu.bootstrap_level(lk, pool, None, None, only_m, form=form)     # G = M = 0: no-op
+    dense = torch.zeros((G + M, lk.n + 1), dtype=torch.int32, device=dev)
+    cemu.bootstrap_level(lk, pool, (ops, ia, ib), (ms, ma, mb), dense, form=form)   # io NULL: row k
     torch.cuda.synchronize()
     assert torch.equal(out_level, out_sep)
+    assert torch.equal(dense, out_level[_t(perm.astype(np.int64), dev)])
     assert torch.equal(only_g, only_g_ref) and torch.equal(only_m, only_m_ref)
     host = to_host_u32(out_level)
     want_g = np.array([Cc._PLAIN[int(o)](int(bits[a]), int(bits[b])) for o, a, b in zip(ops_h, ia_h, ib_h)])
