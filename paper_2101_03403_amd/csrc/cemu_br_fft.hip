@@ -66,6 +66,13 @@ constexpr uint32_t kDigitSignBits = 0x81020000u;
 
 __device__ __forceinline__ d2 cmul(d2 a, d2 b) { return d2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ __forceinline__ d2 cconj(d2 a) { return d2{a.x, -a.y}; }
+// acc + a * b as four fused multiply-adds (written out: the compiler does not
+// fold the accumulate into the multiply's own fused operations, and would
+// spend two multiplies, two fused operations and two adds).
+__device__ __forceinline__ d2 cmac(d2 acc, d2 a, d2 b)
+{
+    return d2{fma(-a.y, b.y, fma(a.x, b.x, acc.x)), fma(a.y, b.x, fma(a.x, b.y, acc.y))};
+}
 
 // Nearest integer of y reduced mod 2^32, for |y| < 2^51: adding 1.5 * 2^52
 // lands in the binade [2^52, 2^53) whose spacing is 1, so the addition itself
@@ -391,8 +398,8 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
                 __builtin_amdgcn_sched_barrier(0);
                 static_for<0, 8>([&](auto sI) {
                     constexpr int sl = decltype(sI)::value;
-                    outA[sl] += cmul(x[sl], kst[sl * 64 + lane]);
-                    outB[sl] += cmul(x[sl], kst[FH + sl * 64 + lane]);
+                    outA[sl] = cmac(outA[sl], x[sl], kst[sl * 64 + lane]);
+                    outB[sl] = cmac(outB[sl], x[sl], kst[FH + sl * 64 + lane]);
                 });
                 __builtin_amdgcn_sched_barrier(0);
             }
