@@ -83,7 +83,8 @@ def parse():
                     help="FFT64 launch shape of the throughput loop (1 = the one-gate-per-workgroup latency kernel)")
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=64, help="gates in the oracle CPU sample")
+    ap.add_argument("--cpu-sample", type=int, default=512,
+                    help="gates in the oracle CPU sample (about 10-15 s of CPU work on 16 threads)")
     ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
     ap.add_argument("--no-shift", action="store_true", help="skip the 32-bit barrel-shifter latency measurement")
     ap.add_argument("--no-emu", action="store_true", help="skip the emulator while-loop run")
