@@ -436,20 +436,24 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
 }
 
 constexpr int LAT_WAVES = 6;   // one wave per digit row (2 components x l = 3)
-constexpr int LAT_EXT = 3 * FN; // negacyclic extension of one ACC component
 
 constexpr int LAT_REGION = 2 * FH;  // d2 per wave: its two partial products, or its transpose scratch
 
-// ACC component c is kept as its negacyclic extension E_c[k], k < 3N:
-// E[k] = ACC[k] for k mod 2N < N and -ACC[k mod N] otherwise, so that
-// (X^a ACC)_j = E[(j - a) mod 2N + ...] is one plain strided read for all
-// j = base + 64 s with base = (lane - a) mod 2N and s < 16.
+// ACC component c is kept as one 16-byte record per coefficient pair
+// (j, j + N/2), j < N/2: (R_j, R_{j+N/2}, ACC_j, ACC_{j+N/2}) with
+// R = X^a ACC for the rotation a of the step about to run, so a digit wave
+// gets D = R - ACC at its 16 coefficients from 8 aligned 16-byte reads.
+// The rotation amounts are known in advance (the bars), so the waves that
+// update ACC write R for the next step directly: ACC_j and ACC_{j+N/2} land
+// at k = (j + a) mod 2N and k + N/2, i.e. in one record r = k mod N/2, as
+// (f, s) = (v0, v1), (-v1, v0), (-v0, -v1) or (v1, -v0) for k / (N/2) =
+// 0, 1, 2, 3 (negacyclic wrap).
 __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 *__restrict__ spec,
                                                                       const uint16_t *__restrict__ bars, int32_t n,
                                                                       uint32_t *__restrict__ ext)
 {
     static_assert(SCR <= LAT_REGION, "scratch fits a region");
-    __shared__ uint32_t accx[2][LAT_EXT];
+    __shared__ __attribute__((aligned(16))) uint32_t zacc[2][4 * FH];
     // region of wave w: its transpose scratch during a transform, then its
     // partial products (output q, slot*64 + lane) at q*FH; region 2 ends up
     // holding the six-row sums
@@ -464,14 +468,21 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     const Tw t0 = make_tw(lane);
     Tw t = t0;
 
-    // ACC = (0, X^{-bbar} v), written as its extension
-    const uint32_t bb = bar[n];
-    for (int k = tid; k < LAT_EXT; k += 64 * LAT_WAVES) {
-        const uint32_t m = (uint32_t)k & (uint32_t)(FN - 1);
-        const uint32_t tt = (m + bb) & (uint32_t)(2 * FN - 1);
-        const uint32_t v = tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
-        accx[0][k] = 0u;
-        accx[1][k] = ((uint32_t)k & (uint32_t)FN) ? 0u - v : v;
+    // ACC = (0, X^{-bbar} v) with the records of step 0 (R = X^{a_0} ACC)
+    const uint32_t bb = bar[n], a0 = bar[0];
+    auto tv = [&](uint32_t m) {   // coefficient m < N of X^{-bbar} v
+        return ((m + bb) & (uint32_t)(2 * FN - 1)) < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+    };
+    for (int e = tid; e < FH; e += 64 * LAT_WAVES) {
+        uint32_t r[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint32_t tt = ((uint32_t)(e + h * FH) - a0) & (uint32_t)(2 * FN - 1);
+            const uint32_t v = tv(tt & (uint32_t)(FN - 1));
+            r[h] = (tt & (uint32_t)FN) ? 0u - v : v;
+        }
+        *reinterpret_cast<uint4 *>(&zacc[0][4 * e]) = uint4{0u, 0u, 0u, 0u};
+        *reinterpret_cast<uint4 *>(&zacc[1][4 * e]) = uint4{r[0], r[1], tv((uint32_t)e), tv((uint32_t)(e + FH))};
     }
     // the two output waves keep their component's own 16 coefficients
     // (j = lane + 64 m + 512 h) in registers
@@ -489,20 +500,23 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     }
     __syncthreads();
 
-    const uint32_t *ec = accx[c];
-    const uint32_t *own = ec + lane;
-    uint32_t a_next = bar[0];
+    const uint4 *zc = reinterpret_cast<const uint4 *>(zacc[c]) + lane;
     for (int i = 0; i < n; ++i) {
-        const uint32_t a = a_next;
-        if (i + 1 < n) a_next = bar[i + 1];
+        // the next step's rotation, applied when the ACC records are written back
+        const uint32_t a_next = i + 1 < n ? (uint32_t)bar[i + 1] : 0u;
         launder(t.tw); launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b);
         // digit jj of D = X^a ACC_c - ACC_c at this lane's 16 coefficients
-        const uint32_t *rot = ec + (((uint32_t)lane - a) & (uint32_t)(2 * FN - 1));
         d2 x[8];
+        // all eight records requested before the first is used (left to
+        // itself the compiler keeps two reads in flight, exposing their latency)
+        uint4 zw[8];
+        static_for<0, 8>([&](auto mI) { zw[decltype(mI)::value] = zc[64 * decltype(mI)::value]; });
+        __builtin_amdgcn_sched_barrier(0);
         static_for<0, 8>([&](auto mI) {
             constexpr int m = decltype(mI)::value;
-            const uint32_t d0 = rot[64 * m] - own[64 * m] + kDigitOffset;
-            const uint32_t d1 = rot[64 * m + FH] - own[64 * m + FH] + kDigitOffset;
+            const uint4 w = zw[m];
+            const uint32_t d0 = w.x - w.z + kDigitOffset;
+            const uint32_t d1 = w.y - w.w + kDigitOffset;
             const double lo = (double)((int32_t)((d0 >> sh) & 127u) - 64);
             const double hi = (double)((int32_t)((d1 >> sh) & 127u) - 64);
             x[m] = cmul(d2{lo, hi}, twist_slot(m));
@@ -543,7 +557,7 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
             d2 y[8];
             static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] = region[2][p * FH + decltype(sI)::value * 64 + lane]; });
             fft_inv(y, scr, lane, t);
-            uint32_t *dst = accx[p] + lane;
+            uint32_t *zq = zacc[p];
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
                 const d2 z = cmul(y[m], cconj(twist_slot(m)));
@@ -551,12 +565,15 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
                 const uint32_t v1 = mine[m + 8] + round_mod32(z.y);
                 mine[m] = v0;
                 mine[m + 8] = v1;
-                dst[64 * m] = v0;
-                dst[64 * m + FN] = 0u - v0;
-                dst[64 * m + 2 * FN] = v0;
-                dst[64 * m + FH] = v1;
-                dst[64 * m + FH + FN] = 0u - v1;
-                dst[64 * m + FH + 2 * FN] = v1;
+                const uint32_t j = (uint32_t)(lane + 64 * m);
+                *reinterpret_cast<uint2 *>(&zq[4 * j + 2]) = uint2{v0, v1};
+                // this pair rotated by the next step's amount (unused after the last step)
+                const uint32_t k = (j + a_next) & (uint32_t)(2 * FN - 1);
+                const uint32_t quad = k / FH;
+                const uint32_t f = (quad & 1u) ? v1 : v0, sc = (quad & 1u) ? v0 : v1;
+                const uint32_t fr = (quad == 1u || quad == 2u) ? 0u - f : f;
+                const uint32_t sr = (quad >= 2u) ? 0u - sc : sc;
+                *reinterpret_cast<uint2 *>(&zq[4 * (k & (uint32_t)(FH - 1))]) = uint2{fr, sr};
             });
         }
         __syncthreads();   // ACC updated
@@ -566,9 +583,10 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     uint32_t *e = ext + g * (FN + 1);
     for (int j = tid; j <= FN; j += 64 * LAT_WAVES) {
         uint32_t v;
-        if (j == 0) v = accx[0][0];
-        else if (j == FN) v = accx[1][0];
-        else v = 0u - accx[0][FN - j];
+        auto accw = [&](int q, int k) { return zacc[q][4 * (k & (FH - 1)) + 2 + (k >= FH)]; };
+        if (j == 0) v = accw(0, 0);
+        else if (j == FN) v = accw(1, 0);
+        else v = 0u - accw(0, FN - j);
         e[j] = v;
     }
 }
