@@ -661,3 +661,29 @@ def test_program_mux_prefix_levels_and_graph(std, dev):
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(to_host_u32(pool), eager), f"graph replay {rep} differs"
+
+
+def test_bootstrap_level_toy_bit_exact(toy, dev):
+    """Toy parameters (N = 512), int8 form: a level of 9 gates and 7 MUXes
+    through cemu_bootstrap_level, every output bit-exact against the
+    oracle's gates and MUX."""
+    lk, ok = toy
+    rng = np.random.default_rng(17)
+    R, G, M = 12, 9, 7
+    say(f"[gpu] bootstrap_level toy G={G} M={M}")
+    bits = rng.integers(0, 2, R).astype(np.uint8)
+    host_in = lk.encrypt(bits, seed=W.ENC_SEED + 41)
+    pool = to_dev(host_in, dev)
+    ops_h = rng.integers(0, 10, G).astype(np.uint8)
+    ia_h, ib_h = (rng.integers(0, R, G).astype(np.int32) for _ in range(2))
+    ms_h, ma_h, mb_h = (rng.integers(0, R, M).astype(np.int32) for _ in range(3))
+    perm = rng.permutation(G + M).astype(np.int32)
+    out = torch.zeros((G + M, lk.n + 1), dtype=torch.int32, device=dev)
+    cemu.bootstrap_level(lk, pool, tuple(_t(x, dev) for x in (ops_h, ia_h, ib_h)),
+                         tuple(_t(x, dev) for x in (ms_h, ma_h, mb_h)), out, io=_t(perm, dev), form="int8")
+    torch.cuda.synchronize()
+    host = to_host_u32(out)
+    _, og = O.bootstrap_batch(ok, ops_h.astype(np.int32), host_in[ia_h], host_in[ib_h], want_extracted=False)
+    om = O.mux_batch(ok, host_in[ms_h], host_in[ma_h], host_in[mb_h])
+    assert np.array_equal(host[perm[:G]], og)
+    assert np.array_equal(host[perm[G:]], om)
