@@ -36,6 +36,13 @@ PEAK_FP64_FLOPS = 78.6e12        # MI355X FP64 vector, flop/s
 # FP64-FFT form per gate: n steps x (8 FFTs of 512 points at 5 n log2 n + twist
 # 6 x 512, plus 12 x 512 complex multiply-adds at 8 flop).
 FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
+# Key switch per gate, as the contraction it runs: K = N t base one-hot rows
+# x 640 columns (n + 1 padded) x 4 limbs x 2 ops; and the key bytes a gate's
+# nonzero digits select (3/4 of the N t digits, n + 1 words each).
+KS_T, KS_BASE = 8, 4
+KS_OPS_PER_GATE = N_ * KS_T * KS_BASE * 640 * 4 * 2
+KS_GATHER_BYTES_PER_GATE = N_ * KS_T * 3 // 4 * (n_ + 1) * 4
+PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 
 
 # HBM bytes per launch of the blind-rotation kernels at B = 4096, from two
@@ -49,6 +56,8 @@ TRAFFIC = {
               "bytes": 486_975 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
     "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "dfef580e980366c5",
              "bytes": 245_915 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
+    "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "f79207ee4fcb2cb6",
+           "bytes": 361_133 * 1024 * 2 + 10_101 * 1024, "batch": 4096},
 }
 
 
@@ -111,11 +120,14 @@ def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample):
     dt = time.time() - t0
     cores = O.num_threads()
     match = int(np.sum(np.all(oout == gpu_out[idx], axis=1)))
+    diff = (gpu_out[idx].astype(np.int64) - oout.astype(np.int64)) % (1 << 32)
+    diff = np.where(diff >= 1 << 31, diff - (1 << 32), diff)
     return {"value": sample / dt, "unit": "gates/s", "cores": cores, "kind": "oracle",
             "sample": f"first {sample} gates of the same 4096-gate batch, same keys and ciphertexts; "
                       f"exact schoolbook products, OpenMP across gates; {dt:.1f} s "
                       f"(oracle keygen {t_keygen:.1f} s not timed)",
-            "bit_exact_vs_gpu": f"{match}/{sample}"}
+            "bit_exact_vs_gpu": f"{match}/{sample}",
+            "max_torus_error_vs_gpu": int(np.abs(diff).max()) if sample else None}
 
 
 def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
@@ -407,6 +419,27 @@ def roofline(form, prof, B, fft_gates_per_wg=8):
             "algorithmic_per_gate": "n*(8*(5*512*9 + 6*512) + 12*512*8) = 1.63e8 FP64 flop"}
 
 
+def key_switch_report(prof, B):
+    """The key switch of the same launches: achieved int8 rate of its
+    contraction, HBM bytes from the committed counters (while the kernel
+    source is the one profiled) over its time, and the key bytes the gates'
+    digits select over its time (a rate the batch reaches by reusing each
+    key row from L2 / MALL across the gates of a tile)."""
+    ms, cnt = prof["key_switch"]
+    if not cnt:
+        return None
+    avg = ms / cnt
+    sec = avg * 1e-3
+    hbm = traffic_bytes("ks", B)
+    return {"kernel": "ks_mfma_kernel<1024, false>", "avg_ms": avg,
+            "int8_TOPs": KS_OPS_PER_GATE * B / sec / 1e12, "frac_int8_peak": KS_OPS_PER_GATE * B / sec / PEAK_INT8_OPS,
+            "hbm_bytes": hbm, "hbm_GBps": hbm / sec / 1e9 if hbm else None,
+            "frac_hbm_peak": hbm / sec / PEAK_HBM_BYTES if hbm else None,
+            "selected_key_bytes_GBps": KS_GATHER_BYTES_PER_GATE * B / sec / 1e9,
+            "per_gate": "contraction 4*N*t*640*4 limbs*2 = 1.68e8 int8 ops; selected key rows "
+                        "N*t*3/4*(n+1)*4 B = 15.5 MB"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -454,6 +487,7 @@ def main():
         res[form] = {
             "value": B / (wall / args.steps), "ms_per_step": wall * 1e3 / args.steps,
             "roofline": roofline(form, prof, B, args.fft_gates_per_wg),
+            "key_switch": key_switch_report(prof, B),
             "kernels": {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()},
             "decrypt_exact": f"{int(np.sum(keys.decrypt(host) == want))}/{B}",
             "output_noise": output_noise(keys, host, want),
@@ -491,7 +525,7 @@ def main():
                                + ("FP64 negacyclic-FFT products" if args.form == "fft64"
                                   else "int8-limb MFMA products"),
                    "form": args.form, "batch": B, "parallelism": "single GPU"},
-        "roofline": primary["roofline"], "cpu_baseline": cpu,
+        "roofline": primary["roofline"], "cpu_baseline": cpu, "key_switch": primary["key_switch"],
         "kernels": primary["kernels"], "decrypt_exact": primary["decrypt_exact"],
         "output_noise": primary["output_noise"], "noise_chain_level2": primary["noise_chain_level2"],
         "forms": {f: {k: v for k, v in r.items() if k != "kernels"} for f, r in res.items()},
