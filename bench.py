@@ -94,7 +94,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512,
                     help="gates in the oracle CPU sample (about 10-15 s of CPU work on 16 threads)")
-    ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD latency measurement")
+    ap.add_argument("--no-add", action="store_true", help="skip the 32-bit ADD / SUB latency measurements")
     ap.add_argument("--no-shift", action="store_true", help="skip the 32-bit barrel-shifter latency measurement")
     ap.add_argument("--no-emu", action="store_true", help="skip the emulator while-loop run")
     ap.add_argument("--no-seq", action="store_true",
@@ -153,11 +153,12 @@ def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
     return wall, cemu.profile_read(keys)
 
 
-def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="gates"):
-    """32-bit Kogge-Stone ADD (Sec. 5.2): `instances` concurrent ADDs with all
-    gates of a level in one launch, the levels (12 with the paper's AND/OR
-    prefix, 7 with the MUX prefix) captured as one hipGraph. Latency = first
-    level launch to last level done; also one instance alone."""
+def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="gates", kind="ADD"):
+    """32-bit Kogge-Stone ADD (Sec. 5.2) or SUB (Sec. 5.3, kind="SUB"):
+    `instances` concurrent instructions with all gates of a level in one
+    launch, the levels (12 with the paper's AND/OR prefix, 7 with the MUX
+    prefix) captured as one hipGraph. Latency = first level launch to last
+    level done; also one instance alone."""
     import torch
     from paper_2101_03403_amd import circuits as Cc, workloads as W
 
@@ -165,7 +166,7 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="ga
     for inst in (instances, 1):
         rng = np.random.default_rng(404 + inst)
         ops = rng.integers(0, 1 << 32, (inst, 2), dtype=np.uint64)
-        cs = [Cc.adder_instance(32, prefix=prefix) for _ in range(inst)]
+        cs = [(Cc.adder_instance if kind == "ADD" else Cc.sub_instance)(32, prefix=prefix) for _ in range(inst)]
         prog = Cc.Program(cs).to_device(dev)
         bits = []
         for a, b in ops:
@@ -189,11 +190,11 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="ga
         host = pool.cpu().numpy().view(np.uint32)
         ok = 0
         for k, (a, b) in enumerate(ops):
-            rows = np.array(cs[k].outputs["sum"]) + prog.offsets[k]
-            ok += int(Cc.bits_to_int(keys.decrypt(host[rows])) == (int(a) + int(b)) % (1 << 32))
+            rows = np.array(cs[k].outputs["sum" if kind == "ADD" else "diff"]) + prog.offsets[k]
+            ok += int(Cc.bits_to_int(keys.decrypt(host[rows])) == Cc.instruction_result(kind, 32, int(a), int(b)))
         ms = float(np.median(times))
         key = "batch" if inst == instances else "single"
-        out[key] = {"instances": inst, "latency_ms": ms, "amortized_ms_per_add": ms / inst,
+        out[key] = {"instances": inst, "latency_ms": ms, "amortized_ms_per_instruction": ms / inst,
                     "gates": prog.num_gates(), "muxes": prog.num_muxes(), "bootstraps": prog.num_bootstraps(),
                     "levels": prog.depth, "bootstraps_per_s": prog.num_bootstraps() / (ms * 1e-3),
                     "decrypt_exact": f"{ok}/{inst}", "level_widths": prog.level_widths(),
@@ -504,6 +505,8 @@ def main():
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_add_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux")
+    rec_sub = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, kind="SUB")
+    rec_sub_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux", kind="SUB")
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
     rec_mix_mux = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner, prefix="mux")
     rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
@@ -533,6 +536,8 @@ def main():
     if rec_add is not None:
         rec["add32"] = rec_add
         rec["add32_mux_prefix"] = rec_add_mux
+        rec["sub32"] = rec_sub
+        rec["sub32_mux_prefix"] = rec_sub_mux
     if rec_mix is not None:
         rec["mixed_stream"] = rec_mix
         rec["mixed_stream_mux_prefix"] = rec_mix_mux
