@@ -395,7 +395,12 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
                 });
                 __builtin_amdgcn_sched_barrier(0);
                 fft_fwd(x, scr, lane, t);
-                __builtin_amdgcn_sched_barrier(0);
+                // The older wave of each SIMD is issued first and runs ahead;
+                // resynchronising before the products keeps the younger one
+                // from ending every row alone (one wave cannot keep the SIMD
+                // busy): 4 % faster. (Moving the stage-visible barrier here
+                // instead, two barriers per row, was slower than three.)
+                __syncthreads();
                 static_for<0, 8>([&](auto sI) {
                     constexpr int sl = decltype(sI)::value;
                     outA[sl] = cmac(outA[sl], x[sl], kst[sl * 64 + lane]);
