@@ -75,8 +75,10 @@ enum {
     CEMU_NUM_GATE_OPS = 10
 };
 
+#define CEMU_MAX_LWE_N 4096
+
 typedef struct cemu_params {
-    int32_t n;         /* LWE dimension of gate ciphertexts                  */
+    int32_t n;         /* LWE dimension of gate ciphertexts: 1..CEMU_MAX_LWE_N */
     int32_t N;         /* TRLWE ring degree: 512 or 1024                      */
     int32_t k;         /* TRLWE mask count: must be 1                        */
     int32_t l;         /* bootstrapping-key gadget length: must be 3          */
@@ -150,8 +152,11 @@ int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int
  * calls records the workspace addresses: size the workspaces first (run the
  * same launches once eagerly), and replay the graph only while no later call
  * on the same cloud key has needed a larger workspace (that reallocates it).
- * Errors: CEMU_ERR_NULL, CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0),
- * CEMU_ERR_PARAM (unknown form), CEMU_ERR_UNSUPPORTED (FFT64 form with
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0, B > 2^40,
+ * or more gates than one launch of the selected blind-rotation shape holds:
+ * a dispatch counts at most 2^32 - 1 work-items, i.e. 11.1M gates for the
+ * latency kernel, 67.1M for the FFT throughput kernels and 134M (8 waves) or
+ * 268M (4 waves) for the int8 form), CEMU_ERR_PARAM (unknown form), CEMU_ERR_UNSUPPORTED (FFT64 form with
  * N != 1024: it is built for the standard ring degree only), CEMU_ERR_OOM,
  * CEMU_ERR_HIP. */
 int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
@@ -159,13 +164,15 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops,
                          int64_t B, void *hip_stream);
 
 /* The same gates without the final key switch: writes the extracted
- * dimension-N samples. out_N: device uint32_t [B][N+1]. */
+ * dimension-N samples. out_N: device uint32_t [B][N+1]. Errors as
+ * cemu_bootstrap_gates. */
 int cemu_blind_rotate_extract(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
                               const int32_t *ia, const int32_t *ib, uint32_t *out_N, int64_t B,
                               void *hip_stream);
 
 /* Key switching of B dimension-N samples to dimension n.
- * in_N: device [B][N+1]; out_n: device [B][n+1]. */
+ * in_N: device [B][N+1]; out_n: device [B][n+1]. Errors: CEMU_ERR_NULL,
+ * CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0 or B > 2^40), CEMU_ERR_HIP. */
 int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *out_n, int64_t B,
                     void *hip_stream);
 
@@ -200,7 +207,8 @@ int cemu_mux(const cemu_cloud_key *ck, int form, const uint32_t *pool_in, const 
  * Every output equals what cemu_bootstrap_gates (k < G) or cemu_mux
  * (k >= G) computes for the same inputs, bit for bit. G = M = 0 is a no-op.
  * Scratch: the workspaces hold G + 2M blind-rotation samples.
- * Errors: CEMU_ERR_RANGE (G < 0 or M < 0), the others as
+ * Errors: CEMU_ERR_RANGE (G < 0, M < 0, G or M > 2^40, or G + 2M blind
+ * rotations beyond one launch, as for cemu_bootstrap_gates), the others as
  * cemu_bootstrap_gates. */
 int cemu_bootstrap_level(const cemu_cloud_key *ck, int form, const uint32_t *pool_in, const uint8_t *ops,
                          const int32_t *ia, const int32_t *ib, int64_t G, const int32_t *ms, const int32_t *ma,
@@ -210,7 +218,8 @@ int cemu_bootstrap_level(const cemu_cloud_key *ck, int form, const uint32_t *poo
  * [P][n+1]: NOT (negation of every word), COPY, and CONSTANT (trivial
  * ciphertext (0,...,0, +-1/8)). src, dst: device int32_t [count] rows; for
  * constant, bits is device uint8_t [count]. No key material is needed, only
- * the dimension n. */
+ * the dimension n (1..CEMU_MAX_LWE_N). Errors: CEMU_ERR_RANGE (count < 0 or
+ * count > 2^40), CEMU_ERR_PARAM (n), CEMU_ERR_NULL, CEMU_ERR_HIP. */
 int cemu_lwe_not(int32_t n, const uint32_t *pool_in, const int32_t *src, uint32_t *pool_out,
                  const int32_t *dst, int64_t count, void *hip_stream);
 int cemu_lwe_copy(int32_t n, const uint32_t *pool_in, const int32_t *src, uint32_t *pool_out,

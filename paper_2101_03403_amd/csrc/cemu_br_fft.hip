@@ -612,6 +612,15 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
 
 }  // namespace
 
+int br_fft_batch_ok(const cemu_cloud_key *ck, int64_t B)
+{
+    // one workgroup per gate (latency kernel) or per FG gates
+    const int fg = ck->tuning.fft_gates_per_wg;
+    const int64_t items = fg == 1 ? B * 64 * LAT_WAVES : (B + fg - 1) / fg * 64 * fg;
+    if (B < 0 || items > (int64_t)0xffffffff) return fail(CEMU_ERR_RANGE, "batch too large for one launch of this shape");
+    return CEMU_OK;
+}
+
 int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
 {
     if (ck->p.N != FN) return fail(CEMU_ERR_UNSUPPORTED, "the FFT64 form is built for N = 1024");
@@ -625,12 +634,13 @@ int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t 
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("bk_fft_prepare launch: ") + hipGetErrorString(e));
     }
-    if (B > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
+    if (const int rc = br_fft_batch_ok(ck, B)) return rc;
+    const int fg = ck->tuning.fft_gates_per_wg;
     const d2 *spec = reinterpret_cast<const d2 *>(ck->d_bkfft);
     if (B == 0) return CEMU_OK;
-    if (ck->tuning.fft_gates_per_wg == 1)
+    if (fg == 1)
         hipLaunchKernelGGL(br_fft_lat_kernel, dim3((unsigned)B), dim3(64 * LAT_WAVES), 0, s, spec, bars, n, ext);
-    else if (ck->tuning.fft_gates_per_wg == 4)
+    else if (fg == 4)
         hipLaunchKernelGGL(br_fft_kernel<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, spec, bars, n, B, ext);
     else
         hipLaunchKernelGGL(br_fft_kernel<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), 0, s, spec, bars, n, B, ext);

@@ -274,10 +274,17 @@ int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint
 
 }  // namespace
 
-int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
+int br_int8_batch_ok(const cemu_cloud_key *ck, int64_t B)
 {
     const int64_t blocks = (B + BR_G - 1) / BR_G;
-    if (blocks > 0x7fffffff) return fail(CEMU_ERR_RANGE, "batch too large");
+    if (B < 0 || blocks * 64 * ck->tuning.int8_waves > (int64_t)0xffffffff)
+        return fail(CEMU_ERR_RANGE, "batch too large for one launch");
+    return CEMU_OK;
+}
+
+int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
+{
+    if (const int rc = br_int8_batch_ok(ck, B)) return rc;
     const int waves = ck->tuning.int8_waves;   // 4 or 8 (validated by cemu_set_tuning)
     int rc;
     if (ck->p.N == 1024) rc = waves == 8 ? launch_shape<1024, 8>(ck, bars, B, ext, s) : launch_shape<1024, 4>(ck, bars, B, ext, s);

@@ -25,6 +25,23 @@ std::string hip_msg(const char *what, hipError_t e)
     return std::string(what) + ": " + hipGetErrorString(e);
 }
 
+// Element-wise kernels walk their index range with a grid stride and their
+// launches cap the grid: a dispatch counts its work-items in 32 bits, so one
+// thread per element would limit a batch to 2^32 / (n + 1) gates. The cap
+// (2^24 threads) is far above what the GPU holds resident.
+constexpr int kElemThreads = 256;
+constexpr int64_t kElemMaxBlocks = 1 << 16;
+
+inline dim3 elem_grid(int64_t total)
+{
+    const int64_t b = (total + kElemThreads - 1) / kElemThreads;
+    return dim3((unsigned)(b < kElemMaxBlocks ? b : kElemMaxBlocks));
+}
+
+#define ELEM_LOOP(idx, total)                                                                   \
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < (total);            \
+         idx += (int64_t)gridDim.x * blockDim.x)
+
 #define CEMU_HIP(call)                                                   \
     do {                                                                 \
         hipError_t e_ = (call);                                          \
@@ -40,25 +57,25 @@ __constant__ int32_t c_gate_w1[CEMU_NUM_GATE_OPS] = {-1, 1, 1, 2, -2, -1, -1, 1,
 __constant__ int32_t c_gate_w2[CEMU_NUM_GATE_OPS] = {-1, 1, 1, 2, -2, -1, 1, -1, 1, -1};
 
 // K1: gate linear combination fused with the modulus switch to Z/2N.
-// One thread per (gate, coefficient); bars is [B][n+1] u16 row-major.
+// One element per (gate, coefficient); bars is [B][n+1] u16 row-major.
 __global__ void lincomb_modswitch_kernel(const uint8_t *__restrict__ ops, const uint32_t *__restrict__ pool,
                                          const int32_t *__restrict__ ia, const int32_t *__restrict__ ib,
                                          int32_t n, int32_t log2_2n, int64_t B, uint16_t *__restrict__ bars)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = n + 1;
-    if (idx >= B * row) return;
-    const int64_t g = idx / row;
-    const int32_t u = (int32_t)(idx - g * row);
-    uint32_t op = ops[g];
-    if (op >= CEMU_NUM_GATE_OPS) op = 0;
-    const uint32_t x1 = pool[(int64_t)ia[g] * row + u];
-    const uint32_t x2 = pool[(int64_t)ib[g] * row + u];
-    uint32_t x = (uint32_t)c_gate_w1[op] * x1 + (uint32_t)c_gate_w2[op] * x2;
-    if (u == n) x += c_gate_kappa[op];
     // nearest integer to x * 2N / 2^32, mod 2N (the shift drops the wrap)
     const uint32_t half = 1u << (31 - log2_2n);
-    bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
+    ELEM_LOOP(idx, B * row) {
+        const int64_t g = idx / row;
+        const int32_t u = (int32_t)(idx - g * row);
+        uint32_t op = ops[g];
+        if (op >= CEMU_NUM_GATE_OPS) op = 0;
+        const uint32_t x1 = pool[(int64_t)ia[g] * row + u];
+        const uint32_t x2 = pool[(int64_t)ib[g] * row + u];
+        uint32_t x = (uint32_t)c_gate_w1[op] * x1 + (uint32_t)c_gate_w2[op] * x2;
+        if (u == n) x += c_gate_kappa[op];
+        bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
+    }
 }
 
 // Multiplexer, first half: the two gates AND(s, a) and ANDNY(s, b) of every
@@ -68,20 +85,20 @@ __global__ void mux_lincomb_kernel(const uint32_t *__restrict__ pool, const int3
                                    const int32_t *__restrict__ ia, const int32_t *__restrict__ ib, int32_t n,
                                    int32_t log2_2n, int64_t B, uint16_t *__restrict__ bars)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = n + 1;
-    if (idx >= 2 * B * row) return;
-    const int64_t g2 = idx / row;
-    const int32_t u = (int32_t)(idx - g2 * row);
-    const bool second = g2 >= B;
-    const int64_t g = second ? g2 - B : g2;
-    const int op = second ? CEMU_ANDNY : CEMU_AND;
-    const uint32_t x1 = pool[(int64_t)is[g] * row + u];
-    const uint32_t x2 = pool[(int64_t)(second ? ib[g] : ia[g]) * row + u];
-    uint32_t x = (uint32_t)c_gate_w1[op] * x1 + (uint32_t)c_gate_w2[op] * x2;
-    if (u == n) x += c_gate_kappa[op];
     const uint32_t half = 1u << (31 - log2_2n);
-    bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
+    ELEM_LOOP(idx, 2 * B * row) {
+        const int64_t g2 = idx / row;
+        const int32_t u = (int32_t)(idx - g2 * row);
+        const bool second = g2 >= B;
+        const int64_t g = second ? g2 - B : g2;
+        const int op = second ? CEMU_ANDNY : CEMU_AND;
+        const uint32_t x1 = pool[(int64_t)is[g] * row + u];
+        const uint32_t x2 = pool[(int64_t)(second ? ib[g] : ia[g]) * row + u];
+        uint32_t x = (uint32_t)c_gate_w1[op] * x1 + (uint32_t)c_gate_w2[op] * x2;
+        if (u == n) x += c_gate_kappa[op];
+        bars[idx] = (uint16_t)((x + half) >> (32 - log2_2n));
+    }
 }
 
 // Multiplexer, second half: ext[g] += ext[B + g] + (0, ..., 0, 1/8). Both
@@ -89,11 +106,11 @@ __global__ void mux_lincomb_kernel(const uint32_t *__restrict__ pool, const int3
 // it is true, so the sum encrypts +-1/8 for the selected bit.
 __global__ void mux_combine_kernel(uint32_t *__restrict__ ext, int32_t N, int64_t B)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = N + 1;
-    if (idx >= B * row) return;
-    const int64_t j = idx - (idx / row) * row;
-    ext[idx] += ext[idx + B * row] + (j == N ? 0x20000000u : 0u);
+    ELEM_LOOP(idx, B * row) {
+        const int64_t j = idx - (idx / row) * row;
+        ext[idx] += ext[idx + B * row] + (j == N ? 0x20000000u : 0u);
+    }
 }
 
 // K3: key switching N -> n. A workgroup takes KS_G samples; thread t owns
@@ -181,34 +198,39 @@ __global__ __launch_bounds__(KS_THREADS) void key_switch_kernel(const uint32_t *
 __global__ void lwe_not_kernel(int32_t n, const uint32_t *__restrict__ in, const int32_t *__restrict__ src,
                                uint32_t *__restrict__ out, const int32_t *__restrict__ dst, int64_t count)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = n + 1;
-    if (idx >= count * row) return;
-    const int64_t e = idx / row, u = idx - e * row;
-    out[(int64_t)dst[e] * row + u] = 0u - in[(int64_t)src[e] * row + u];
+    ELEM_LOOP(idx, count * row) {
+        const int64_t e = idx / row, u = idx - e * row;
+        out[(int64_t)dst[e] * row + u] = 0u - in[(int64_t)src[e] * row + u];
+    }
 }
 
 __global__ void lwe_copy_kernel(int32_t n, const uint32_t *__restrict__ in, const int32_t *__restrict__ src,
                                 uint32_t *__restrict__ out, const int32_t *__restrict__ dst, int64_t count)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = n + 1;
-    if (idx >= count * row) return;
-    const int64_t e = idx / row, u = idx - e * row;
-    out[(int64_t)dst[e] * row + u] = in[(int64_t)src[e] * row + u];
+    ELEM_LOOP(idx, count * row) {
+        const int64_t e = idx / row, u = idx - e * row;
+        out[(int64_t)dst[e] * row + u] = in[(int64_t)src[e] * row + u];
+    }
 }
 
 __global__ void lwe_constant_kernel(int32_t n, const uint8_t *__restrict__ bits, uint32_t *__restrict__ out,
                                     const int32_t *__restrict__ dst, int64_t count)
 {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = n + 1;
-    if (idx >= count * row) return;
-    const int64_t e = idx / row, u = idx - e * row;
-    out[(int64_t)dst[e] * row + u] = u == n ? (bits[e] ? 0x20000000u : 0xE0000000u) : 0u;
+    ELEM_LOOP(idx, count * row) {
+        const int64_t e = idx / row, u = idx - e * row;
+        out[(int64_t)dst[e] * row + u] = u == n ? (bits[e] ? 0x20000000u : 0xE0000000u) : 0u;
+    }
 }
 
 inline bool misaligned(const void *p) { return ((uintptr_t)p & 3u) != 0; }
+
+// Largest batch an entry point accepts: keeps every element count and byte
+// size computed from it far from int64 / size_t overflow (real batches are
+// bounded much earlier by device memory).
+constexpr int64_t kMaxBatch = (int64_t)1 << 40;
 
 // CEMU_KS_VALU=1 selects the VALU key-switching kernel (for comparison).
 bool ks_valu_forced()
@@ -254,12 +276,9 @@ int launch_lincomb(const cemu_cloud_key *ck, const uint8_t *ops, const uint32_t 
                    const int32_t *ib, int64_t B, uint16_t *bars, hipStream_t s)
 {
     const int32_t n = ck->p.n;
-    const int64_t total = B * (n + 1);
-    const int threads = 256;
-    const int64_t blocks = (total + threads - 1) / threads;
     void *ev = prof_begin(ck, s);
-    hipLaunchKernelGGL(lincomb_modswitch_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, ops, pool, ia, ib, n,
-                       log2_of(2 * ck->p.N), B, bars);
+    hipLaunchKernelGGL(lincomb_modswitch_kernel, elem_grid(B * (n + 1)), dim3(kElemThreads), 0, s, ops, pool, ia, ib,
+                       n, log2_of(2 * ck->p.N), B, bars);
     CEMU_HIP(hipGetLastError());
     prof_end(ck, 0, s, ev);
     return CEMU_OK;
@@ -287,6 +306,13 @@ int launch_key_switch(const cemu_cloud_key *ck, const uint32_t *ext, const int32
     CEMU_HIP(hipGetLastError());
     prof_end(ck, 3, s, ev);
     return CEMU_OK;
+}
+
+// The blind-rotation launch for B rotations fits one dispatch (checked
+// before anything is allocated or launched).
+int check_br_batch(const cemu_cloud_key *ck, int form, int64_t B)
+{
+    return form == CEMU_FORM_INT8 ? br_int8_batch_ok(ck, B) : br_fft_batch_ok(ck, B);
 }
 
 int check_device(const cemu_cloud_key *ck)
@@ -328,22 +354,19 @@ int run_level(cemu_cloud_key *ck, int form, const uint32_t *pool, const uint8_t 
               const int32_t *io, uint32_t *pool_out, hipStream_t s)
 {
     const int32_t n = ck->p.n, N = ck->p.N;
-    const int threads = 256;
     int rc;
     if (G > 0 && (rc = launch_lincomb(ck, ops, pool, ia, ib, G, ck->d_bars, s))) return rc;
     if (M > 0) {
-        const int64_t blocks = (2 * M * (n + 1) + threads - 1) / threads;
         void *ev = prof_begin(ck, s);
-        hipLaunchKernelGGL(mux_lincomb_kernel, dim3((unsigned)blocks), dim3(threads), 0, s, pool, ms, ma, mb, n,
-                           log2_of(2 * N), M, ck->d_bars + G * (n + 1));
+        hipLaunchKernelGGL(mux_lincomb_kernel, elem_grid(2 * M * (n + 1)), dim3(kElemThreads), 0, s, pool, ms, ma, mb,
+                           n, log2_of(2 * N), M, ck->d_bars + G * (n + 1));
         CEMU_HIP(hipGetLastError());
         prof_end(ck, 0, s, ev);
     }
     rc = run_br(ck, form, ck->d_ext, G + 2 * M, s);
     if (rc) return rc;
     if (M > 0) {
-        const int64_t blocks = (M * (N + 1) + threads - 1) / threads;
-        hipLaunchKernelGGL(mux_combine_kernel, dim3((unsigned)blocks), dim3(threads), 0, s,
+        hipLaunchKernelGGL(mux_combine_kernel, elem_grid(M * (N + 1)), dim3(kElemThreads), 0, s,
                            ck->d_ext + G * (N + 1), N, M);
         CEMU_HIP(hipGetLastError());
     }
@@ -448,6 +471,7 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ckc, int form, const uint8_t *ops
     if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
     if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
     if (B == 0) return CEMU_OK;
+    if (B > kMaxBatch) return fail(CEMU_ERR_RANGE, "batch too large");
     if (!ops || !pool_in || !ia || !ib || !pool_out) return fail(CEMU_ERR_NULL, "NULL device buffer");
     if (misaligned(pool_in) || misaligned(ia) || misaligned(ib) || misaligned(pool_out) || (io && misaligned(io)))
         return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
@@ -455,6 +479,7 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ckc, int form, const uint8_t *ops
     std::lock_guard<std::mutex> lock(ck->mu);
     int rc = check_device(ck);
     if (rc) return rc;
+    if ((rc = check_br_batch(ck, form, B))) return rc;
     rc = ensure_workspace(ck, B, true);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
@@ -471,7 +496,7 @@ int cemu_mux(const cemu_cloud_key *ckc, int form, const uint32_t *pool_in, const
     if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
     if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
     if (B == 0) return CEMU_OK;
-    if (B > ((int64_t)1 << 40)) return fail(CEMU_ERR_RANGE, "batch too large");
+    if (B > kMaxBatch) return fail(CEMU_ERR_RANGE, "batch too large");
     if (!pool_in || !is || !ia || !ib || !pool_out) return fail(CEMU_ERR_NULL, "NULL device buffer");
     if (misaligned(pool_in) || misaligned(is) || misaligned(ia) || misaligned(ib) || misaligned(pool_out) ||
         (io && misaligned(io)))
@@ -480,6 +505,7 @@ int cemu_mux(const cemu_cloud_key *ckc, int form, const uint32_t *pool_in, const
     std::lock_guard<std::mutex> lock(ck->mu);
     int rc = check_device(ck);
     if (rc) return rc;
+    if ((rc = check_br_batch(ck, form, 2 * B))) return rc;
     rc = ensure_workspace(ck, 2 * B, true);
     if (rc) return rc;
     return run_level(ck, form, pool_in, nullptr, nullptr, nullptr, 0, is, ia, ib, B, io, pool_out,
@@ -495,7 +521,7 @@ int cemu_bootstrap_level(const cemu_cloud_key *ckc, int form, const uint32_t *po
     if (G < 0 || M < 0) return fail(CEMU_ERR_RANGE, "G < 0 or M < 0");
     if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
     if (G == 0 && M == 0) return CEMU_OK;
-    if (G > ((int64_t)1 << 40) || M > ((int64_t)1 << 40)) return fail(CEMU_ERR_RANGE, "batch too large");
+    if (G > kMaxBatch || M > kMaxBatch) return fail(CEMU_ERR_RANGE, "batch too large");
     if (!pool_in || !pool_out || (G > 0 && (!ops || !ia || !ib)) || (M > 0 && (!ms || !ma || !mb)))
         return fail(CEMU_ERR_NULL, "NULL device buffer");
     if (misaligned(pool_in) || misaligned(pool_out) || (io && misaligned(io)) ||
@@ -505,6 +531,7 @@ int cemu_bootstrap_level(const cemu_cloud_key *ckc, int form, const uint32_t *po
     std::lock_guard<std::mutex> lock(ck->mu);
     int rc = check_device(ck);
     if (rc) return rc;
+    if ((rc = check_br_batch(ck, form, G + 2 * M))) return rc;
     rc = ensure_workspace(ck, G + 2 * M, true);
     if (rc) return rc;
     return run_level(ck, form, pool_in, ops, ia, ib, G, ms, ma, mb, M, io, pool_out, (hipStream_t)hip_stream);
@@ -518,6 +545,7 @@ int cemu_blind_rotate_extract(const cemu_cloud_key *ckc, int form, const uint8_t
     if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
     if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
     if (B == 0) return CEMU_OK;
+    if (B > kMaxBatch) return fail(CEMU_ERR_RANGE, "batch too large");
     if (!ops || !pool_in || !ia || !ib || !out_N) return fail(CEMU_ERR_NULL, "NULL device buffer");
     if (misaligned(pool_in) || misaligned(ia) || misaligned(ib) || misaligned(out_N))
         return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
@@ -525,6 +553,7 @@ int cemu_blind_rotate_extract(const cemu_cloud_key *ckc, int form, const uint8_t
     std::lock_guard<std::mutex> lock(ck->mu);
     int rc = check_device(ck);
     if (rc) return rc;
+    if ((rc = check_br_batch(ck, form, B))) return rc;
     rc = ensure_workspace(ck, B, false);
     if (rc) return rc;
     return run_blind_rotate(ck, form, ops, pool_in, ia, ib, out_N, B, (hipStream_t)hip_stream);
@@ -536,6 +565,7 @@ int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *ou
     if (!ck) return fail(CEMU_ERR_NULL, "cloud key is NULL");
     if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
     if (B == 0) return CEMU_OK;
+    if (B > kMaxBatch) return fail(CEMU_ERR_RANGE, "batch too large");
     if (!in_N || !out_n) return fail(CEMU_ERR_NULL, "NULL device buffer");
     if (misaligned(in_N) || misaligned(out_n)) return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
     std::lock_guard<std::mutex> lock(const_cast<cemu_cloud_key *>(ck)->mu);
@@ -606,17 +636,16 @@ static int launch_rowwise(int which, int32_t n, const uint32_t *in, const int32_
 {
     clear_error();
     if (count < 0) return fail(CEMU_ERR_RANGE, "count < 0");
-    if (n < 1) return fail(CEMU_ERR_PARAM, "n must be >= 1");
+    if (n < 1 || n > CEMU_MAX_LWE_N) return fail(CEMU_ERR_PARAM, "n must be in [1, CEMU_MAX_LWE_N]");
     if (count == 0) return CEMU_OK;
+    if (count > kMaxBatch) return fail(CEMU_ERR_RANGE, "count too large");
     if (!out || !dst || (which < 2 && (!in || !src)) || (which == 2 && !bits))
         return fail(CEMU_ERR_NULL, "NULL device buffer");
-    const int64_t total = count * (n + 1);
-    const int threads = 256;
-    const dim3 grid((unsigned)((total + threads - 1) / threads));
+    const dim3 grid = elem_grid(count * (n + 1)), block(kElemThreads);
     hipStream_t s = (hipStream_t)hip_stream;
-    if (which == 0) hipLaunchKernelGGL(lwe_not_kernel, grid, dim3(threads), 0, s, n, in, src, out, dst, count);
-    else if (which == 1) hipLaunchKernelGGL(lwe_copy_kernel, grid, dim3(threads), 0, s, n, in, src, out, dst, count);
-    else hipLaunchKernelGGL(lwe_constant_kernel, grid, dim3(threads), 0, s, n, bits, out, dst, count);
+    if (which == 0) hipLaunchKernelGGL(lwe_not_kernel, grid, block, 0, s, n, in, src, out, dst, count);
+    else if (which == 1) hipLaunchKernelGGL(lwe_copy_kernel, grid, block, 0, s, n, in, src, out, dst, count);
+    else hipLaunchKernelGGL(lwe_constant_kernel, grid, block, 0, s, n, bits, out, dst, count);
     CEMU_HIP(hipGetLastError());
     return CEMU_OK;
 }

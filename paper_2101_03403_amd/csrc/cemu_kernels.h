@@ -13,6 +13,12 @@ namespace cemu {
 int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
 int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
 
+// CEMU_OK if one launch of the key's current shape for the form holds B
+// blind rotations (a dispatch counts at most 2^32 - 1 work-items), else
+// CEMU_ERR_RANGE with the message set. The launchers check it too.
+int br_int8_batch_ok(const cemu_cloud_key *ck, int64_t B);
+int br_fft_batch_ok(const cemu_cloud_key *ck, int64_t B);
+
 // Key switching of B extracted samples as an int8 MFMA contraction; output
 // row io[g] (or g) of out. Requires ks_mfma_supported(ck->p).
 int launch_ks_mfma(const cemu_cloud_key *ck, const uint32_t *ext, const int32_t *io, uint32_t *out, int64_t B,

@@ -687,3 +687,107 @@ def test_bootstrap_level_toy_bit_exact(toy, dev):
     om = O.mux_batch(ok, host_in[ms_h], host_in[ma_h], host_in[mb_h])
     assert np.array_equal(host[perm[:G]], og)
     assert np.array_equal(host[perm[G:]], om)
+
+
+def _plain_gates(ops, a, b):
+    """NAND / AND / OR / XOR (the throughput mix) on plaintext bits, vectorised."""
+    a = a.astype(np.uint8)
+    b = b.astype(np.uint8)
+    r = np.select([ops == cemu.NAND, ops == cemu.AND, ops == cemu.OR, ops == cemu.XOR],
+                  [1 - (a & b), a & b, a | b, a ^ b], default=255)
+    assert (r != 255).all()
+    return r.astype(np.uint8)
+
+
+def test_batches_beyond_one_grid_pass(std, dev):
+    """The element-wise kernels (linear combination, the MUX halves and
+    combine, NOT / COPY / CONSTANT) walk their range with a grid stride over
+    at most 2^24 threads; batches of more than 2^24 elements take several
+    passes. Gates and MUXes: one large call equals, word for word, the same
+    work split in two calls that each fit one pass, and every decryption is
+    exact. Batches beyond one blind-rotation launch are refused with a range
+    error before anything is allocated or launched."""
+    lk, _ = std
+    row = lk.n + 1
+    one_pass = 1 << 24
+
+    # NOT / COPY / CONSTANT on random words
+    cnt = 30000
+    assert cnt * row > one_pass
+    say(f"[gpu] grid stride: NOT / COPY / CONSTANT count={cnt}")
+    rng = np.random.default_rng(5)
+    host = rng.integers(0, 1 << 32, (cnt, row), dtype=np.uint64).astype(np.uint32)
+    src = to_dev(host, dev)
+    perm = rng.permutation(cnt).astype(np.int32)
+    idx = torch.arange(cnt, dtype=torch.int32, device=dev)
+    dst = torch.from_numpy(perm).to(dev)
+    dnot = torch.zeros_like(src)
+    dcopy = torch.zeros_like(src)
+    dconst = torch.zeros_like(src)
+    bits = rng.integers(0, 2, cnt).astype(np.uint8)
+    cemu.lwe_not(lk.n, src, idx, dnot, dst)
+    cemu.lwe_copy(lk.n, src, idx, dcopy, dst)
+    cemu.lwe_constant(lk.n, torch.from_numpy(bits).to(dev), dconst, dst)
+    torch.cuda.synchronize()
+    want_copy = np.empty_like(host)
+    want_copy[perm] = host
+    assert np.array_equal(to_host_u32(dcopy), want_copy)
+    assert np.array_equal(to_host_u32(dnot), (0 - want_copy.astype(np.uint64)).astype(np.uint32))
+    want_const = np.zeros_like(host)
+    want_const[perm, lk.n] = np.where(bits == 1, 0x20000000, 0xE0000000).astype(np.uint32)
+    assert np.array_equal(to_host_u32(dconst), want_const)
+
+    # gates: lincomb over B * (n + 1) > 2^24 elements
+    B = 30000
+    assert B * row > one_pass and (B // 2) * row <= one_pass
+    say(f"[gpu] grid stride: {B} gates, fft64, one call against two")
+    ops, a, b = W.gate_batch(B, seed=77)
+    c1 = lk.encrypt(a, seed=78)
+    c2 = lk.encrypt(b, seed=78, first_index=B)
+    pool = to_dev(np.concatenate([c1, c2]), dev)
+    ops_t = torch.from_numpy(np.ascontiguousarray(ops.astype(np.uint8))).to(dev)
+    ia = torch.arange(B, dtype=torch.int32, device=dev)
+    ib = ia + B
+    big = torch.zeros((B, row), dtype=torch.int32, device=dev)
+    cemu.bootstrap_gates(lk, ops_t, pool, ia, ib, big, form="fft64")
+    halves = torch.zeros_like(big)
+    h = B // 2
+    cemu.bootstrap_gates(lk, ops_t[:h], pool, ia[:h], ib[:h], halves[:h], form="fft64")
+    cemu.bootstrap_gates(lk, ops_t[h:], pool, ia[h:], ib[h:], halves[h:], form="fft64")
+    torch.cuda.synchronize()
+    got = to_host_u32(big)
+    assert np.array_equal(got, to_host_u32(halves))
+    assert np.array_equal(lk.decrypt(got), _plain_gates(ops, a, b))
+
+    # MUX: its lincomb covers 2M (n + 1) and its combine M (N + 1) > 2^24 elements
+    M = 17000
+    assert M * (lk.N + 1) > one_pass and 2 * (M // 2) * row <= one_pass
+    say(f"[gpu] grid stride: {M} MUXes, fft64, one call against two")
+    mbits, cts = _mux_inputs(lk, M, 93)
+    mpool = to_dev(np.concatenate(cts), dev)
+    rows = torch.arange(M, dtype=torch.int32, device=dev)
+    mbig = torch.zeros((M, row), dtype=torch.int32, device=dev)
+    cemu.mux(lk, mpool, rows, rows + M, rows + 2 * M, mbig, form="fft64")
+    mhalves = torch.zeros_like(mbig)
+    hm = M // 2
+    cemu.mux(lk, mpool, rows[:hm], rows[:hm] + M, rows[:hm] + 2 * M, mhalves[:hm], form="fft64")
+    cemu.mux(lk, mpool, rows[hm:], rows[hm:] + M, rows[hm:] + 2 * M, mhalves[hm:], form="fft64")
+    torch.cuda.synchronize()
+    mgot = to_host_u32(mbig)
+    assert np.array_equal(mgot, to_host_u32(mhalves))
+    assert np.array_equal(lk.decrypt(mgot), np.where(mbits[0] == 1, mbits[1], mbits[2]))
+
+    # range errors, returned before any allocation or launch
+    p = C.c_void_p(pool.data_ptr())
+    o = C.c_void_p(ops_t.data_ptr())
+    rc = cemu.lib().cemu_bootstrap_gates(lk.ck, 1, o, p, p, p, None, p, C.c_int64(1 << 41), None)
+    assert rc == cemu.lib().cemu_bootstrap_gates(lk.ck, 1, o, p, p, p, None, p, C.c_int64(-1), None) != 0
+    saved = cemu.get_tuning(lk)
+    try:
+        cemu.set_tuning(lk, fft_gates_per_wg=1)
+        too_many = (0xFFFFFFFF // 384) + 1          # one workgroup of 384 threads per gate
+        rc2 = cemu.lib().cemu_bootstrap_gates(lk.ck, 1, o, p, p, p, None, p, C.c_int64(too_many), None)
+        assert rc2 == rc
+        assert "too large" in cemu.lib().cemu_last_error().decode()
+    finally:
+        cemu.set_tuning(lk, **saved)
