@@ -523,6 +523,10 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     for (int i = 0; i < n; ++i) {
         // the next step's rotation, applied when the ACC records are written back
         const uint32_t a_next = i + 1 < n ? (uint32_t)bar[i + 1] : 0u;
+        // waves 4 and 5 share a SIMD with waves 0 and 1, which the arbiter
+        // issues first; raising them until the first transpose of their
+        // forward transform lets each pair finish that phase together
+        if (p >= 4) __builtin_amdgcn_s_setprio(1);
         launder(t.tw); launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b);
         // digit jj of D = X^a ACC_c - ACC_c at this lane's 16 coefficients
         d2 x[8];
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
             x[m] = cmul(d2{lo, hi}, twist_slot(m));
         });
         __builtin_amdgcn_sched_barrier(0);
-        fft_fwd(x, scr, lane, t);
+        fft_fwd<true>(x, scr, lane, t);
         __builtin_amdgcn_sched_barrier(0);
         // partial products of this digit row with the two key spectra, into
         // this wave's region (its transform is done; LDS ops of a wave are
