@@ -52,12 +52,12 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 # comments and whitespace removed, so that comment edits keep it), else
 # reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "98f6062d2959f859",
-              "bytes": 486_969 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
-    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "dfef580e980366c5",
-             "bytes": 245_917 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "f7db1ce027a1e49b",
+              "bytes": 486_966 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "9d3cada7d3eac37b",
+             "bytes": 245_920 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
     "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "f79207ee4fcb2cb6",
-           "bytes": 361_916 * 1024 * 2 + 10_153 * 1024, "batch": 4096},
+           "bytes": 361_598 * 1024 * 2 + 10_183 * 1024, "batch": 4096},
 }
 
 
