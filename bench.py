@@ -108,8 +108,44 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample):
-    """The CPU oracle, as it stands, on a bounded sample of the same batch."""
+def cpu_add32_latency(okeys, seed=404):
+    """One 32-bit ADD (the paper's AND/OR prefix, 12 levels) through the CPU
+    oracle, level by level: each level's gates in one batch, OpenMP across
+    them (the level structure of the paper's own parallel ADD, Sec. 5.2).
+    Returns (seconds, decrypted sum correct)."""
+    from oracle import oracle as O
+    from paper_2101_03403_amd import circuits as Cc
+    rng = np.random.default_rng(seed)
+    a, b = (int(x) for x in rng.integers(0, 1 << 32, 2, dtype=np.uint64))
+    c = Cc.adder_instance(32)
+    prog = Cc.Program([c])
+    n = okeys.params.n
+    pool = np.zeros((prog.rows, n + 1), np.uint32)
+    bits = np.asarray(Cc.int_to_bits(a, 32) + Cc.int_to_bits(b, 32), np.uint8)
+    pool[prog.input_rows] = O.encrypt_bits(okeys, bits, seed=seed)
+    for bit, row in zip(prog.consts[0], prog.consts[1]):
+        pool[row] = 0
+        pool[row, n] = 0x20000000 if bit else 0xE0000000
+    t0 = time.time()
+    for L in prog.levels:
+        src, dst = L.nots
+        pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
+        if L.ops.shape[0]:
+            _, out = O.bootstrap_batch(okeys, L.ops.astype(np.int32), pool[L.ia], pool[L.ib], want_extracted=False)
+            pool[L.io] = out
+        if L.num_muxes:
+            ms, ma, mb, mo = L.mux
+            pool[mo] = O.mux_batch(okeys, pool[ms], pool[ma], pool[mb])
+    src, dst = prog.tail_nots
+    pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
+    dt = time.time() - t0
+    got = Cc.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[np.array(c.outputs["sum"])]))
+    return dt, got == Cc.instruction_result("ADD", 32, a, b)
+
+
+def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample, add32=True):
+    """The CPU oracle, as it stands, on a bounded sample of the same batch;
+    also one gate alone (one thread works on it) and one 32-bit ADD."""
     from oracle import oracle as O
     idx = np.arange(sample)
     t0 = time.time()
@@ -122,12 +158,22 @@ def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample):
     match = int(np.sum(np.all(oout == gpu_out[idx], axis=1)))
     diff = (gpu_out[idx].astype(np.int64) - oout.astype(np.int64)) % (1 << 32)
     diff = np.where(diff >= 1 << 31, diff - (1 << 32), diff)
-    return {"value": sample / dt, "unit": "gates/s", "cores": cores, "kind": "oracle",
-            "sample": f"first {sample} gates of the same 4096-gate batch, same keys and ciphertexts; "
-                      f"exact schoolbook products, OpenMP across gates; {dt:.1f} s "
-                      f"(oracle keygen {t_keygen:.1f} s not timed)",
-            "bit_exact_vs_gpu": f"{match}/{sample}",
-            "max_torus_error_vs_gpu": int(np.abs(diff).max()) if sample else None}
+    t0 = time.time()
+    O.bootstrap_batch(okeys, ops[:1].astype(np.int32), c1[:1], c2[:1], want_extracted=False)
+    one_gate = time.time() - t0
+    res = {"value": sample / dt, "unit": "gates/s", "cores": cores, "kind": "oracle",
+           "sample": f"first {sample} gates of the same 4096-gate batch, same keys and ciphertexts; "
+                     f"exact schoolbook products, OpenMP across gates; {dt:.1f} s "
+                     f"(oracle keygen {t_keygen:.1f} s not timed)",
+           "bit_exact_vs_gpu": f"{match}/{sample}",
+           "max_torus_error_vs_gpu": int(np.abs(diff).max()) if sample else None,
+           "one_gate_ms": one_gate * 1e3}
+    if add32:
+        t_add, ok = cpu_add32_latency(okeys)
+        res["add32_latency_ms"] = t_add * 1e3
+        res["add32"] = ("one 32-bit ADD, the paper's AND/OR prefix (483 gates, 12 levels), each level's gates "
+                        f"across the {cores} threads; decrypted sum {'correct' if ok else 'WRONG'}")
+    return res
 
 
 def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
@@ -517,7 +563,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(W.KEY_SEED, ops, c1, c2, outs[args.form], min(args.cpu_sample, B))
+        cpu = cpu_baseline(W.KEY_SEED, ops, c1, c2, outs[args.form], min(args.cpu_sample, B), add32=not args.no_add)
 
     rec = {
         "metric": METRIC, "value": primary["value"], "unit": "gates/s", "n_gpus": 1, "steps": args.steps,
