@@ -52,8 +52,8 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 # comments and whitespace removed, so that comment edits keep it), else
 # reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "f7db1ce027a1e49b",
-              "bytes": 486_966 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "f4e3779f4670c50b",
+              "bytes": 486_963 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
     "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "9d3cada7d3eac37b",
              "bytes": 245_920 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
     "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "f79207ee4fcb2cb6",

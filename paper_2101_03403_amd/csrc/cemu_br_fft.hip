@@ -642,12 +642,37 @@ int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t 
     const int fg = ck->tuning.fft_gates_per_wg;
     const d2 *spec = reinterpret_cast<const d2 *>(ck->d_bkfft);
     if (B == 0) return CEMU_OK;
-    if (fg == 1)
-        hipLaunchKernelGGL(br_fft_lat_kernel, dim3((unsigned)B), dim3(64 * LAT_WAVES), 0, s, spec, bars, n, ext);
-    else if (fg == 4)
-        hipLaunchKernelGGL(br_fft_kernel<4>, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, s, spec, bars, n, B, ext);
-    else
-        hipLaunchKernelGGL(br_fft_kernel<8>, dim3((unsigned)((B + 7) / 8)), dim3(512), 0, s, spec, bars, n, B, ext);
+    auto launch = [&](int shape, const uint16_t *b, int64_t cnt, uint32_t *x) {
+        if (shape == 1)
+            hipLaunchKernelGGL(br_fft_lat_kernel, dim3((unsigned)cnt), dim3(64 * LAT_WAVES), 0, s, spec, b, n, x);
+        else if (shape == 4)
+            hipLaunchKernelGGL(br_fft_kernel<4>, dim3((unsigned)((cnt + 3) / 4)), dim3(256), 0, s, spec, b, n, cnt, x);
+        else
+            hipLaunchKernelGGL(br_fft_kernel<8>, dim3((unsigned)((cnt + 7) / 8)), dim3(512), 0, s, spec, b, n, cnt, x);
+    };
+    // Every shape runs one workgroup per CU, so a launch proceeds in rounds of
+    // fg * CUs gates, and a round costs the same however few of its
+    // workgroups are busy. A batch of k full rounds plus a short tail r runs
+    // the tail as its own launch of a smaller shape whenever that is cheaper
+    // than one more round. Measured round times on MI355X (630 steps):
+    // latency kernel (CUs gates) 2.54 ms, 4 gates per workgroup 8.8 ms,
+    // 8 gates per workgroup 10.8 ms; so a tail of up to 3 CUs gates goes to
+    // the latency kernel, and behind 8-gate rounds one of up to 4 CUs gates
+    // to the 4-gate shape. Outputs do not depend on the shape.
+    const int64_t cus = ck->num_cus;
+    int64_t full = B;
+    int tail_shape = 0;
+    if (cus > 0 && fg > 1) {
+        const int64_t round = fg * cus;
+        const int64_t r = B % round;
+        if (B >= round && r > 0) {
+            if (r <= 3 * cus) tail_shape = 1;
+            else if (fg == 8 && r <= 4 * cus) tail_shape = 4;
+            if (tail_shape) full = B - r;
+        }
+    }
+    launch(fg, bars, full, ext);
+    if (tail_shape) launch(tail_shape, bars + full * (int64_t)(n + 1), B - full, ext + full * (int64_t)(FN + 1));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("br_fft_kernel launch: ") + hipGetErrorString(e));
     return CEMU_OK;

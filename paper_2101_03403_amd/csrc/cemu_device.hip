@@ -403,6 +403,8 @@ int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const 
                      const std::vector<uint8_t> &ksk_mfma)
 {
     CEMU_HIP(hipGetDevice(&ck->device));
+    if (hipDeviceGetAttribute(&ck->num_cus, hipDeviceAttributeMultiprocessorCount, ck->device) != hipSuccess)
+        ck->num_cus = 0;
     if (hipMalloc(&ck->d_bk8, bk8.size()) != hipSuccess) return fail(CEMU_ERR_OOM, "device allocation (BK) failed");
     if (hipMalloc(&ck->d_ksk, ksk.size() * sizeof(uint32_t)) != hipSuccess) {
         release_cloud_key(ck);

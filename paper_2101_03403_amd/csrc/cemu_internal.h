@@ -19,6 +19,7 @@ struct cemu_secret_key {
 struct cemu_cloud_key {
     cemu_params p;
     int device = -1;
+    int num_cus = 0;   // compute units of that device (0: unknown)
     // Bootstrapping key, int8-limb layout. For step i, digit row r = c*l + j,
     // output component q and limb kappa, 2N bytes R with
     //   R[u] = limb_kappa( E[2N-1-u] ),  E[t] = BK[t-N] (t >= N), -BK[t] (t < N),

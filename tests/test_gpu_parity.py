@@ -791,3 +791,30 @@ def test_batches_beyond_one_grid_pass(std, dev):
         assert "too large" in cemu.lib().cemu_last_error().decode()
     finally:
         cemu.set_tuning(lk, **saved)
+
+
+def test_fft_round_tail_split(std, dev):
+    """Every FFT shape runs one workgroup per CU, so a batch of k full rounds
+    plus a short tail launches the tail separately on a smaller shape (the
+    latency kernel, or 4 gates per workgroup behind 8-gate rounds). Batches
+    sized from the device's CU count take each path; every output equals,
+    word for word, the latency kernel's output for the whole batch, and every
+    decryption is exact."""
+    lk, _ = std
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    saved = cemu.get_tuning(lk)
+    try:
+        for fg, B in ((8, 8 * cus + cus // 2 + 3), (8, 8 * cus + 3 * cus + cus // 2), (4, 4 * cus + 2 * cus + 1),
+                      (8, 16 * cus + 5)):
+            say(f"[gpu] fft tail split: fg={fg} B={B} (CUs {cus})")
+            ops, a, b = W.gate_batch(B, seed=300 + B)
+            c1 = lk.encrypt(a, seed=301)
+            c2 = lk.encrypt(b, seed=301, first_index=B)
+            cemu.set_tuning(lk, fft_gates_per_wg=fg)
+            _, got = run_gates(lk, ops, c1, c2, dev, form="fft64", want_ext=False)
+            cemu.set_tuning(lk, fft_gates_per_wg=1)
+            _, ref = run_gates(lk, ops, c1, c2, dev, form="fft64", want_ext=False)
+            assert np.array_equal(got, ref)
+            assert np.array_equal(lk.decrypt(got), _plain_gates(ops, a, b))
+    finally:
+        cemu.set_tuning(lk, **saved)
