@@ -123,14 +123,31 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def _dptr(t):
-    """Device pointer of a torch tensor (or None)."""
+def _dptr(t, what="tensor", kind=None, rows=None, width=None, min_rows=None):
+    """Device pointer of a contiguous GPU tensor (or None), after checking what
+    the library will read it as: kind "words" (int32 / uint32 ciphertext
+    words), "rows" (int32 row indices) or "u8" (op codes, bits); `rows` = the
+    exact length of a 1-D array; `width` = the row length of a 2-D array,
+    `min_rows` its least number of rows. A mismatch raises instead of letting
+    the device read the memory as something else."""
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("expected a GPU tensor")
+        raise ValueError(f"{what}: expected a GPU tensor")
     if not t.is_contiguous():
-        raise ValueError("expected a contiguous tensor")
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if kind is not None:
+        import torch
+        ok = {"words": (torch.int32, getattr(torch, "uint32", torch.int32)), "rows": (torch.int32,),
+              "u8": (torch.uint8,)}[kind]
+        if t.dtype not in ok:
+            raise TypeError(f"{what}: dtype {t.dtype}, expected {' or '.join(str(d) for d in ok)}")
+    if rows is not None and (t.dim() != 1 or t.shape[0] != rows):
+        raise ValueError(f"{what}: expected shape [{rows}], got {list(t.shape)}")
+    if min_rows is not None and (t.shape[0] if t.dim() else 0) < min_rows:
+        raise ValueError(f"{what}: needs at least {min_rows} rows, got shape {list(t.shape)}")
+    if width is not None and t.numel() > 0 and (t.dim() != 2 or t.shape[1] != width):
+        raise ValueError(f"{what}: expected rows of {width} words, got shape {list(t.shape)}")
     return C.c_void_p(t.data_ptr())
 
 
@@ -244,29 +261,44 @@ def keygen(p=STD, seed: int = 0) -> Keys:
 
 
 # ------------------------------------------------------------------ device side
+def _gate_args(keys, ops, pool_in, ia, ib, B):
+    n1 = keys.n + 1
+    return (_dptr(ops, "ops", "u8", rows=B), _dptr(pool_in, "pool_in", "words", width=n1, min_rows=1 if B else None),
+            _dptr(ia, "ia", "rows", rows=B), _dptr(ib, "ib", "rows", rows=B))
+
+
 def bootstrap_gates(keys: Keys, ops, pool_in, ia, ib, pool_out, io=None, form="int8", stream=None):
     """Batched bootstrapped gates; see cemu_bootstrap_gates in include/cemu.h."""
     B = int(ops.shape[0])
-    _check(lib().cemu_bootstrap_gates(keys.ck, FORMS[form], _dptr(ops), _dptr(pool_in), _dptr(ia), _dptr(ib),
-                                      _dptr(io), _dptr(pool_out), B, _stream(stream)))
+    _check(lib().cemu_bootstrap_gates(keys.ck, FORMS[form], *_gate_args(keys, ops, pool_in, ia, ib, B),
+                                      _dptr(io, "io", "rows", rows=B),
+                                      _dptr(pool_out, "pool_out", "words", width=keys.n + 1,
+                                            min_rows=B if io is None else None),
+                                      B, _stream(stream)))
 
 
 def blind_rotate_extract(keys: Keys, ops, pool_in, ia, ib, out_N, form="int8", stream=None):
     B = int(ops.shape[0])
-    _check(lib().cemu_blind_rotate_extract(keys.ck, FORMS[form], _dptr(ops), _dptr(pool_in), _dptr(ia), _dptr(ib),
-                                           _dptr(out_N), B, _stream(stream)))
+    _check(lib().cemu_blind_rotate_extract(keys.ck, FORMS[form], *_gate_args(keys, ops, pool_in, ia, ib, B),
+                                           _dptr(out_N, "out_N", "words", width=keys.N + 1, min_rows=B),
+                                           B, _stream(stream)))
 
 
 def key_switch(keys: Keys, in_N, out_n, stream=None):
     B = int(in_N.shape[0])
-    _check(lib().cemu_key_switch(keys.ck, _dptr(in_N), _dptr(out_n), B, _stream(stream)))
+    _check(lib().cemu_key_switch(keys.ck, _dptr(in_N, "in_N", "words", width=keys.N + 1, min_rows=B),
+                                 _dptr(out_n, "out_n", "words", width=keys.n + 1, min_rows=B), B, _stream(stream)))
 
 
 def mux(keys: Keys, pool_in, isel, ia, ib, pool_out, io=None, form="int8", stream=None):
     """Batched homomorphic MUX (isel ? ia : ib); see cemu_mux in include/cemu.h."""
     B = int(isel.shape[0])
-    _check(lib().cemu_mux(keys.ck, FORMS[form], _dptr(pool_in), _dptr(isel), _dptr(ia), _dptr(ib), _dptr(io),
-                          _dptr(pool_out), B, _stream(stream)))
+    n1 = keys.n + 1
+    _check(lib().cemu_mux(keys.ck, FORMS[form], _dptr(pool_in, "pool_in", "words", width=n1, min_rows=1 if B else None),
+                          _dptr(isel, "isel", "rows", rows=B), _dptr(ia, "ia", "rows", rows=B),
+                          _dptr(ib, "ib", "rows", rows=B), _dptr(io, "io", "rows", rows=B),
+                          _dptr(pool_out, "pool_out", "words", width=n1, min_rows=B if io is None else None),
+                          B, _stream(stream)))
 
 
 def bootstrap_level(keys: Keys, pool_in, gates, muxes, pool_out, io=None, form="int8", stream=None):
@@ -277,24 +309,38 @@ def bootstrap_level(keys: Keys, pool_in, gates, muxes, pool_out, io=None, form="
     ms, ma, mb = muxes if muxes is not None else (None, None, None)
     G = int(ops.shape[0]) if ops is not None else 0
     M = int(ms.shape[0]) if ms is not None else 0
-    _check(lib().cemu_bootstrap_level(keys.ck, FORMS[form], _dptr(pool_in), _dptr(ops), _dptr(ia), _dptr(ib), G,
-                                      _dptr(ms), _dptr(ma), _dptr(mb), M, _dptr(io), _dptr(pool_out),
+    n1 = keys.n + 1
+    _check(lib().cemu_bootstrap_level(keys.ck, FORMS[form],
+                                      _dptr(pool_in, "pool_in", "words", width=n1, min_rows=1 if G + M else None),
+                                      _dptr(ops, "ops", "u8", rows=G), _dptr(ia, "ia", "rows", rows=G),
+                                      _dptr(ib, "ib", "rows", rows=G), G,
+                                      _dptr(ms, "isel", "rows", rows=M), _dptr(ma, "ma", "rows", rows=M),
+                                      _dptr(mb, "mb", "rows", rows=M), M, _dptr(io, "io", "rows", rows=G + M),
+                                      _dptr(pool_out, "pool_out", "words", width=n1,
+                                            min_rows=G + M if io is None else None),
                                       _stream(stream)))
 
 
+def _rowwise_args(n, pool_in, src, pool_out, dst):
+    cnt = int(src.shape[0])
+    return (_dptr(pool_in, "pool_in", "words", width=n + 1, min_rows=1 if cnt else None),
+            _dptr(src, "src", "rows", rows=cnt),
+            _dptr(pool_out, "pool_out", "words", width=n + 1), _dptr(dst, "dst", "rows", rows=cnt), cnt)
+
+
 def lwe_not(n: int, pool_in, src, pool_out, dst, stream=None):
-    _check(lib().cemu_lwe_not(n, _dptr(pool_in), _dptr(src), _dptr(pool_out), _dptr(dst), int(src.shape[0]),
-                              _stream(stream)))
+    _check(lib().cemu_lwe_not(n, *_rowwise_args(n, pool_in, src, pool_out, dst), _stream(stream)))
 
 
 def lwe_copy(n: int, pool_in, src, pool_out, dst, stream=None):
-    _check(lib().cemu_lwe_copy(n, _dptr(pool_in), _dptr(src), _dptr(pool_out), _dptr(dst), int(src.shape[0]),
-                               _stream(stream)))
+    _check(lib().cemu_lwe_copy(n, *_rowwise_args(n, pool_in, src, pool_out, dst), _stream(stream)))
 
 
 def lwe_constant(n: int, bits, pool_out, dst, stream=None):
-    _check(lib().cemu_lwe_constant(n, _dptr(bits), _dptr(pool_out), _dptr(dst), int(dst.shape[0]),
-                                   _stream(stream)))
+    cnt = int(dst.shape[0])
+    _check(lib().cemu_lwe_constant(n, _dptr(bits, "bits", "u8", rows=cnt),
+                                   _dptr(pool_out, "pool_out", "words", width=n + 1),
+                                   _dptr(dst, "dst", "rows", rows=cnt), cnt, _stream(stream)))
 
 
 def version() -> str:

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_2101_03403_amd import cemu
@@ -60,3 +61,57 @@ def test_null_and_range_errors():
     assert L.cemu_encrypt(None, None, 0, 0, 0, None) == -2
     assert L.cemu_export_keys(None, None, None, None, None, None) == 0
     assert cemu.version().startswith("cemu")
+
+
+class _FakeDeviceTensor:
+    """Stands in for a contiguous GPU tensor: the binding's pointer marshalling
+    reads only these attributes."""
+    is_cuda = True
+
+    def __init__(self, shape, dtype):
+        self.shape = tuple(shape)
+        self.dtype = dtype
+
+    def is_contiguous(self):
+        return True
+
+    def dim(self):
+        return len(self.shape)
+
+    def numel(self):
+        return int(np.prod(self.shape)) if self.shape else 1
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_binding_checks_dtypes_and_shapes():
+    """What the device will read an argument as is checked before the call:
+    dtype per kind, exact length of index arrays, row width and least row
+    count of ciphertext arrays; empty arrays (never read) pass the width check."""
+    torch = pytest.importorskip("torch")
+    from paper_2101_03403_amd import cemu
+    F = _FakeDeviceTensor
+    assert cemu._dptr(None) is None
+    assert cemu._dptr(F((5,), torch.int32), "ia", "rows", rows=5).value == 4096
+    assert cemu._dptr(F((7, 631), torch.int32), "pool", "words", width=631, min_rows=7).value == 4096
+    assert cemu._dptr(F((0,), torch.int32), "pool", "words", width=631).value == 4096
+    with pytest.raises(TypeError):
+        cemu._dptr(F((5,), torch.int64), "ia", "rows", rows=5)
+    with pytest.raises(TypeError):
+        cemu._dptr(F((5,), torch.int32), "ops", "u8", rows=5)
+    with pytest.raises(TypeError):
+        cemu._dptr(F((5, 631), torch.float32), "pool", "words", width=631)
+    with pytest.raises(ValueError):
+        cemu._dptr(F((4,), torch.int32), "ia", "rows", rows=5)
+    with pytest.raises(ValueError):
+        cemu._dptr(F((5, 1), torch.int32), "ia", "rows", rows=5)
+    with pytest.raises(ValueError):
+        cemu._dptr(F((5, 1025), torch.int32), "pool", "words", width=631)
+    with pytest.raises(ValueError):
+        cemu._dptr(F((4, 631), torch.int32), "pool_out", "words", width=631, min_rows=5)
+    with pytest.raises(ValueError):
+        cemu._dptr(F((0,), torch.int32), "pool_in", "words", width=631, min_rows=1)
+    cpu = torch.zeros(3, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        cemu._dptr(cpu, "ia", "rows", rows=3)
