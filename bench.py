@@ -490,7 +490,7 @@ def key_switch_report(prof, B):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU runs are not supported",
+        print(json.dumps({"error": "the benchmark runs on exactly one GPU; several GPUs are not supported",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
