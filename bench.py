@@ -33,6 +33,12 @@ N_, n_, ROWS = 1024, 630, 6
 INT8_OPS_PER_GATE = n_ * ROWS * 2 * N_ * N_ * 4 * 2
 PEAK_INT8_OPS = 5.0e15          # MI355X dense int8 MFMA, ops/s
 PEAK_FP64_FLOPS = 78.6e12        # MI355X FP64 vector, flop/s
+# The same peaks as measured on MI355X with independent-chain throughput
+# probes at the kernels' occupancy (two waves per SIMD, one workgroup per CU):
+# FP64 FMA 69.6 TFLOP/s, v_mfma_i32_16x16x64_i8 4.9e15 op/s (short bursts, at
+# full clock). Reported beside the spec peaks.
+MEASURED_FP64_FLOPS = 69.6e12
+MEASURED_INT8_OPS = 4.9e15
 # FP64-FFT form per gate: n steps x (8 FFTs of 512 points at 5 n log2 n + twist
 # 6 x 512, plus 12 x 512 complex multiply-adds at 8 flop).
 FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
@@ -454,6 +460,7 @@ def roofline(form, prof, B, fft_gates_per_wg=8):
         ach = INT8_OPS_PER_GATE * B / (avg * 1e-3)
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s",
                 "frac": ach / PEAK_INT8_OPS, "traffic": traffic_bytes("int8", B), "kernel": "br_int8_kernel<1024, 8>",
+                "measured_peak": MEASURED_INT8_OPS / 1e12, "frac_measured": ach / MEASURED_INT8_OPS,
                 "avg_ms": avg, "algorithmic_per_launch": INT8_OPS_PER_GATE * B,
                 "algorithmic_per_gate": "n*2l*2*N^2*4 limbs*2 = 6.34e10 int8 ops"}
     ms, cnt = prof["blind_rotate_fft64"]
@@ -462,6 +469,7 @@ def roofline(form, prof, B, fft_gates_per_wg=8):
     return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
             "frac": ach / PEAK_FP64_FLOPS, "traffic": traffic_bytes("fft64", B) if fft_gates_per_wg == 8 else None,
             "kernel": FFT_KERNEL[fft_gates_per_wg],
+            "measured_peak": MEASURED_FP64_FLOPS / 1e12, "frac_measured": ach / MEASURED_FP64_FLOPS,
             "avg_ms": avg, "algorithmic_per_launch": FFT_FLOP_PER_GATE * B,
             "algorithmic_per_gate": "n*(8*(5*512*9 + 6*512) + 12*512*8) = 1.63e8 FP64 flop"}
 
