@@ -559,6 +559,8 @@ def main():
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_add_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux")
+    # the same ADD with every level on the int8-MFMA form (the two forms' latencies side by side)
+    rec_add_int8 = None if (args.no_add or args.only) else add32_latency(keys, dev, "int8", reps=2)
     rec_sub = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, kind="SUB")
     rec_sub_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux", kind="SUB")
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
@@ -590,6 +592,8 @@ def main():
     if rec_add is not None:
         rec["add32"] = rec_add
         rec["add32_mux_prefix"] = rec_add_mux
+        if rec_add_int8 is not None:
+            rec["add32_int8_form"] = rec_add_int8
         rec["sub32"] = rec_sub
         rec["sub32_mux_prefix"] = rec_sub_mux
     if rec_mix is not None:
