@@ -559,8 +559,17 @@ def main():
         tuner = Autotuner(keys)
     rec_add = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner)
     rec_add_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux")
-    # the same ADD with every level on the int8-MFMA form (the two forms' latencies side by side)
-    rec_add_int8 = None if (args.no_add or args.only) else add32_latency(keys, dev, "int8", reps=2)
+    # the same ADD with every level on the int8-MFMA form (the two forms' latencies side by side);
+    # its launch shape (16 gates or one gate per workgroup) is tuned per level width among int8 shapes only
+    tuner_i8 = None
+    if tuner is not None and not (args.no_add or args.only):
+        from paper_2101_03403_amd.autotune import Autotuner
+        tuner_i8 = Autotuner(keys, forms=("int8",))
+    rec_add_int8 = None if (args.no_add or args.only) else add32_latency(keys, dev, "int8", reps=2, tuner=tuner_i8)
+    if rec_add_int8 is not None and tuner_i8 is not None:
+        rec_add_int8["form"] = "int8 only, launch shape autotuned per level width"
+        rec_add_int8["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner_i8.measurements.get(b)}
+                                    for b, c in sorted(tuner_i8.table.items())}
     rec_sub = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, kind="SUB")
     rec_sub_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux", kind="SUB")
     rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)

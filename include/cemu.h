@@ -241,6 +241,10 @@ void cemu_free_cloud_key(cemu_cloud_key *ck);
 
 /* Launch configuration of the blind-rotation kernels (per cloud key).
  * int8_waves: waves per workgroup of the int8-MFMA kernel, 4 or 8 (default 8).
+ * int8_gates_per_wg: gates per workgroup of the int8-MFMA kernel: 16 (default;
+ *   the gates fill the MFMA columns and share each streamed key row), or 1: the
+ *   latency kernel, one gate per workgroup, for batches too narrow to fill the
+ *   GPU (the key limbs fill the columns instead). 0 selects 16.
  * fft_gates_per_wg: gates per workgroup of the FFT64 kernel, 4 (one wave per
  *   SIMD, 512 registers each) or 8 (two waves per SIMD; default), or 1: the
  *   latency kernel, one gate per workgroup of 6 waves (one wave per gadget
@@ -256,7 +260,8 @@ void cemu_free_cloud_key(cemu_cloud_key *ck);
 typedef struct cemu_tuning {
     int32_t int8_waves;
     int32_t fft_gates_per_wg;
-    int32_t reserved[6];
+    int32_t int8_gates_per_wg;
+    int32_t reserved[5];
 } cemu_tuning;
 int cemu_get_tuning(const cemu_cloud_key *ck, cemu_tuning *t);
 int cemu_set_tuning(cemu_cloud_key *ck, const cemu_tuning *t);

@@ -3,7 +3,7 @@
 For a cloud key and a batch size it measures every candidate launch
 configuration -- product form (FP64-FFT or int8-MFMA) x its tile choice
 (FFT: 8 or 4 gates per workgroup, or the one-gate-per-workgroup latency
-kernel; int8: 8 or 4 waves per workgroup) -- on a
+kernel; int8: 16 gates or one gate per workgroup, 8 or 4 waves) -- on a
 synthetic batch of that size, keeps the fastest, and caches the choice per
 (parameter set, batch-size bucket) in memory and optionally in a JSON file.
 Kernel timing uses the library's own HIP-event profiling (cemu_profile_*),
@@ -26,8 +26,10 @@ CANDIDATES = (
     ("fft64", {"fft_gates_per_wg": 8}),
     ("fft64", {"fft_gates_per_wg": 4}),
     ("fft64", {"fft_gates_per_wg": 1}),
-    ("int8", {"int8_waves": 8}),
-    ("int8", {"int8_waves": 4}),
+    ("int8", {"int8_waves": 8, "int8_gates_per_wg": 16}),
+    ("int8", {"int8_waves": 4, "int8_gates_per_wg": 16}),
+    ("int8", {"int8_waves": 8, "int8_gates_per_wg": 1}),
+    ("int8", {"int8_waves": 4, "int8_gates_per_wg": 1}),
 )
 MIN_BUCKET, MAX_BUCKET = 16, 4096
 

@@ -38,7 +38,8 @@ class CemuError(RuntimeError):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("int8_waves", C.c_int32), ("fft_gates_per_wg", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("int8_waves", C.c_int32), ("fft_gates_per_wg", C.c_int32), ("int8_gates_per_wg", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class Params(C.Structure):
@@ -227,14 +228,21 @@ class Keys:
 def get_tuning(keys: Keys) -> dict:
     t = Tuning()
     _check(lib().cemu_get_tuning(keys.ck, C.byref(t)))
-    return {"int8_waves": t.int8_waves, "fft_gates_per_wg": t.fft_gates_per_wg}
+    return {"int8_waves": t.int8_waves, "fft_gates_per_wg": t.fft_gates_per_wg,
+            "int8_gates_per_wg": t.int8_gates_per_wg}
 
 
-def set_tuning(keys: Keys, int8_waves: int | None = None, fft_gates_per_wg: int | None = None):
+def set_tuning(keys: Keys, int8_waves: int | None = None, fft_gates_per_wg: int | None = None,
+               int8_gates_per_wg: int | None = None):
+    """Change the key's launch shapes; arguments left as None keep their value.
+    A tuning dict that names only some fields (as the autotuner's candidates
+    do) therefore leaves the others as they were: callers that switch shapes
+    pass every field they rely on."""
     cur = get_tuning(keys)
     t = Tuning()
     t.int8_waves = cur["int8_waves"] if int8_waves is None else int8_waves
     t.fft_gates_per_wg = cur["fft_gates_per_wg"] if fft_gates_per_wg is None else fft_gates_per_wg
+    t.int8_gates_per_wg = cur["int8_gates_per_wg"] if int8_gates_per_wg is None else int8_gates_per_wg
     _check(lib().cemu_set_tuning(keys.ck, C.byref(t)))
 
 

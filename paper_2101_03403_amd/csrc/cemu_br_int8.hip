@@ -263,9 +263,201 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
     }
 }
 
+// Latency kernel (narrow circuit levels): one gate per workgroup, so a level
+// of G gates keeps G compute units busy instead of G / 16. With one gate the
+// digits cannot fill the MFMA's 16 columns, so the roles are swapped: the A
+// operand is the negacyclic Toeplitz matrix of the gate's own digit row,
+//   T_p[m][k] = E_p[m - k],  E_p[s] = d_p[s] (s >= 0), -d_p[s + N] (s < 0),
+// kept in LDS as X_p[v] = E_p[v - N], v in [0, 2N) (digits are int8, so the
+// negated half is exact), and the B operand holds the key: column
+// n = 4 q + kappa (n < 8) is limb kappa of BK_i[p][q], columns 8..15 are
+// zero. One 16x16x64 MFMA thus produces every limb of both outputs; the
+// limbs are recombined across the four lanes of a quad (shift by 8 kappa,
+// two DPP adds) and each wave adds its share into ACC with LDS integer
+// atomics, which wrap modulo 2^32 like the sum itself, so the order of the
+// adds does not matter and the result is bit-exact. Inside a lane's 16-byte
+// group the k order is reversed in both operands (k = k0 + 16 g + 15 - t for
+// byte t), which turns the key's reversed storage (BK[m] at byte N - 1 - m)
+// into one aligned 16-byte load per K-tile and leaves X in natural order.
+// Waves: component c (its 3 digit rows), output half mh (N/2 rows), and for
+// WAVES = 8 a half ks of the K-tiles of each row.
+template <int N, int WAVES>
+struct LatShape {
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int KS = WAVES / 4;            // K-splits per (component, output half)
+    static constexpr int MT = N / 32;               // 16-row M-tiles per wave (N/2 rows)
+    static constexpr int KT = N / 64 / KS;          // 64-wide K-tiles per wave and digit row
+    static constexpr int NDELTA = MT + 4 * (KT - 1);
+    static constexpr int XROW = 2 * N + 16;         // bytes per extended digit row, + read slack
+    static_assert(WAVES == 4 || WAVES == 8, "waves");
+    static_assert(KT >= 1 && MT >= 1, "shape");
+};
+
+// acc[a] += T_tile(a, b) * B_tile(b) for the wave's K-tiles b; fragment di
+// serves the pairs with a - 4 b = di - 4 (KT - 1) and sits 16 bytes above
+// fragment di - 1.
+template <int N, int WAVES>
+__device__ __forceinline__ void lat_mfma_block(const uint32_t *__restrict__ pr, uint32_t shift,
+                                               v4i (&acc)[LatShape<N, WAVES>::MT],
+                                               const v4i (&bf)[LatShape<N, WAVES>::KT])
+{
+    using S = LatShape<N, WAVES>;
+    uint32_t w0 = pr[0], w1 = pr[1], w2 = pr[2], w3 = pr[3], w4 = pr[4];
+    static_for<0, S::NDELTA>([&](auto dI) {
+        constexpr int di = decltype(dI)::value;
+        const v4i fr = v4i{(int)__builtin_amdgcn_alignbyte(w1, w0, shift), (int)__builtin_amdgcn_alignbyte(w2, w1, shift),
+                           (int)__builtin_amdgcn_alignbyte(w3, w2, shift), (int)__builtin_amdgcn_alignbyte(w4, w3, shift)};
+        uint32_t n1 = 0, n2 = 0, n3 = 0, n4 = 0;
+        if constexpr (di + 1 < S::NDELTA) {
+            n1 = pr[4 * di + 5];
+            n2 = pr[4 * di + 6];
+            n3 = pr[4 * di + 7];
+            n4 = pr[4 * di + 8];
+        }
+        static_for<0, S::KT>([&](auto bI) {
+            constexpr int b = decltype(bI)::value;
+            constexpr int a = di - 4 * (S::KT - 1) + 4 * b;
+            if constexpr (a >= 0 && a < S::MT) acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[a], 0, 0, 0);
+        });
+        w0 = w4;
+        w1 = n1;
+        w2 = n2;
+        w3 = n3;
+        w4 = n4;
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+template <int N, int WAVES>
+__global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_t *__restrict__ bk8,
+                                                                    const uint16_t *__restrict__ bars, int32_t n,
+                                                                    uint32_t *__restrict__ ext)
+{
+    using S = LatShape<N, WAVES>;
+    __shared__ __attribute__((aligned(16))) uint32_t acc_s[2][N];
+    __shared__ __attribute__((aligned(16))) uint32_t xs[BR_ROWS][S::XROW / 4];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ks = wave % S::KS, mh = (wave / S::KS) & 1, c = wave / (2 * S::KS);
+    const int col = lane & 15, g4 = lane >> 4;
+    const int64_t g = blockIdx.x;   // the grid has exactly one workgroup per gate
+    const uint16_t *bar = bars + g * (int64_t)(n + 1);
+
+    // ACC = (0, X^{-bbar} v), v = (1/8) sum_j X^j.
+    const uint32_t bb = bar[n];
+    for (int m = tid; m < N; m += S::THREADS) {
+        const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * N - 1);
+        acc_s[0][m] = 0u;
+        acc_s[1][m] = tt < (uint32_t)N ? 0x20000000u : 0xE0000000u;
+    }
+
+    // A fragment source of this lane (byte offset in X_p, 1 <= s0 and the
+    // last fragment ends at byte 2N - 1).
+    const int s0 = N + 16 * S::MT * mh - 64 * S::KT * ks + col - 16 * g4 - 15 - 64 * (S::KT - 1);
+    const uint32_t frag_shift = (uint32_t)(s0 & 3);
+    const int frag_dw = s0 >> 2;
+
+    // B fragments: limb kappa of BK_i[p][q] for k in the lane's 16-byte group,
+    // read reversed from the key (byte N - 16 - k0 - 16 g4 .. + 15); columns
+    // 8..15 stay zero.
+    const bool bcol = col < 8;
+    const size_t bplane = bcol ? (size_t)col * (2 * N) : 0;   // plane (q, kappa) = (col >> 2, col & 3)
+    auto load_b = [&](int step, int row, v4i (&dst)[S::KT]) {
+        const uint8_t *src = bk8 + ((size_t)step * BR_ROWS + row) * (2 * 4 * 2 * N) + bplane;
+        static_for<0, S::KT>([&](auto bI) {
+            constexpr int b = decltype(bI)::value;
+            const int u0 = N - 16 - 64 * (S::KT * ks + b) - 16 * g4;
+            const u4 v = bcol ? *reinterpret_cast<const u4 *>(src + u0) : u4{0u, 0u, 0u, 0u};
+            dst[b] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
+        });
+    };
+    v4i nb[S::KT];
+    load_b(0, 3 * c, nb);
+
+    for (int i = 0; i < n; ++i) {
+        const uint32_t a = bar[i];
+        __syncthreads();   // ACC of the previous step complete; X consumed
+        // Extended digit rows of D = X^a ACC_c - ACC_c, four coefficients per item.
+        for (int e = tid; e < N / 2; e += S::THREADS) {
+            const int cc = e / (N / 4), k4 = e - cc * (N / 4);
+            const u4 own = *reinterpret_cast<const u4 *>(&acc_s[cc][4 * k4]);
+            const uint32_t un[4] = {own.x, own.y, own.z, own.w};
+            uint32_t word[3] = {0u, 0u, 0u};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t tt = ((uint32_t)(4 * k4 + t) - a) & (uint32_t)(2 * N - 1);
+                uint32_t v = acc_s[cc][tt & (uint32_t)(N - 1)];
+                v = (tt & (uint32_t)N) ? 0u - v : v;
+                const uint32_t y = v - un[t] + kDigitOffset;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) word[j] |= ((y >> (32 - 7 * (j + 1))) & 127u) << (8 * t);
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                // bytes f = d + 64 in [0, 128): d = (f + 64) ^ 0x80, -d = (0xC0 - f) ^ 0x80, no carries
+                xs[3 * cc + j][N / 4 + k4] = (word[j] + 0x40404040u) ^ 0x80808080u;
+                xs[3 * cc + j][k4] = (0xC0C0C0C0u - word[j]) ^ 0x80808080u;
+            }
+        }
+        __syncthreads();   // digit rows visible, every read of ACC done
+
+        v4i acc[S::MT];
+        static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] = v4i{0, 0, 0, 0}; });
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            v4i bf[S::KT];
+            static_for<0, S::KT>([&](auto bI) { bf[decltype(bI)::value] = nb[decltype(bI)::value]; });
+            // next (step, row); past the last step reload step 0 (unused)
+            const int ni = j < 2 ? i : (i + 1 < n ? i + 1 : 0);
+            load_b(ni, 3 * c + (j < 2 ? j + 1 : 0), nb);
+            lat_mfma_block<N, WAVES>(&xs[3 * c + j][frag_dw], frag_shift, acc, bf);
+        }
+        // Delta_q[m] = sum_kappa 2^(8 kappa) C[m][4 q + kappa]: the four limbs
+        // of an output row sit in the four lanes of a quad (lanes 4q .. 4q+3 of
+        // a 16-lane row), each lane holding rows 4 g4 + e, e = 0..3. A
+        // reduce-scatter over the quad (exchange with lane ^ 1, then lane ^ 2)
+        // leaves lane kappa with the full sum of row e = kappa, so one atomic
+        // add per lane and tile updates ACC_q (lanes 8..15 of a row hold the
+        // zero columns and stay out).
+        const uint32_t lsh = 8u * (uint32_t)(lane & 3);
+        const bool odd = (lane & 1) != 0, hi2 = (lane & 2) != 0, writer = (lane & 8) == 0;
+        uint32_t *accq = acc_s[(lane >> 2) & 1] + 4 * g4 + (lane & 3);
+        static_for<0, S::MT>([&](auto tI) {
+            constexpr int t = decltype(tI)::value;
+            const uint32_t v0 = (uint32_t)acc[t][0] << lsh, v1 = (uint32_t)acc[t][1] << lsh;
+            const uint32_t v2 = (uint32_t)acc[t][2] << lsh, v3 = (uint32_t)acc[t][3] << lsh;
+            // The selects come before the cross-lane moves, which every lane
+            // executes: a DPP read of a lane outside the exec mask yields 0,
+            // so the moves must not sit under lane-dependent branches.
+            // keep rows e = 2h + (lane & 1), pass the other two to lane ^ 1 (quad_perm [1,0,3,2])
+            const uint32_t z0 = (odd ? v1 : v0) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(odd ? v0 : v1), 0xB1, 0xF, 0xF, false);
+            const uint32_t z1 = (odd ? v3 : v2) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(odd ? v2 : v3), 0xB1, 0xF, 0xF, false);
+            // keep row e = lane & 3, pass the other to lane ^ 2 (quad_perm [2,3,0,1])
+            const uint32_t r = (hi2 ? z1 : z0) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(hi2 ? z0 : z1), 0x4E, 0xF, 0xF, false);
+            if (writer) atomicAdd(accq + 16 * (S::MT * mh + t), r);
+        });
+    }
+    __syncthreads();
+
+    // Sample extraction: a'_0 = A_0, a'_j = -A_{N-j}, b' = B_0.
+    uint32_t *out = ext + g * (N + 1);
+    for (int jj = tid; jj <= N; jj += S::THREADS) {
+        uint32_t v;
+        if (jj == 0) v = acc_s[0][0];
+        else if (jj == N) v = acc_s[1][0];
+        else v = 0u - acc_s[0][N - jj];
+        out[jj] = v;
+    }
+}
+
 template <int N, int WAVES>
 int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
 {
+    if (ck->tuning.int8_gates_per_wg == 1) {
+        hipLaunchKernelGGL((br_int8_lat_kernel<N, WAVES>), dim3((unsigned)B), dim3(64 * WAVES), 0, s, ck->d_bk8, bars,
+                           ck->p.n, ext);
+        return CEMU_OK;
+    }
     const int64_t blocks = (B + BR_G - 1) / BR_G;
     hipLaunchKernelGGL((br_int8_kernel<N, WAVES>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, ck->d_bk8, bars,
                        ck->p.n, B, ext);
@@ -276,7 +468,8 @@ int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint
 
 int br_int8_batch_ok(const cemu_cloud_key *ck, int64_t B)
 {
-    const int64_t blocks = (B + BR_G - 1) / BR_G;
+    // one workgroup per gate (latency kernel) or per BR_G gates
+    const int64_t blocks = ck->tuning.int8_gates_per_wg == 1 ? B : (B + BR_G - 1) / BR_G;
     if (B < 0 || blocks * 64 * ck->tuning.int8_waves > (int64_t)0xffffffff)
         return fail(CEMU_ERR_RANGE, "batch too large for one launch");
     return CEMU_OK;
@@ -285,6 +478,7 @@ int br_int8_batch_ok(const cemu_cloud_key *ck, int64_t B)
 int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
 {
     if (const int rc = br_int8_batch_ok(ck, B)) return rc;
+    if (B == 0) return CEMU_OK;
     const int waves = ck->tuning.int8_waves;   // 4 or 8 (validated by cemu_set_tuning)
     int rc;
     if (ck->p.N == 1024) rc = waves == 8 ? launch_shape<1024, 8>(ck, bars, B, ext, s) : launch_shape<1024, 4>(ck, bars, B, ext, s);

@@ -591,8 +591,11 @@ int cemu_set_tuning(cemu_cloud_key *ck, const cemu_tuning *t)
     if (t->int8_waves != 4 && t->int8_waves != 8) return fail(CEMU_ERR_PARAM, "int8_waves must be 4 or 8");
     if (t->fft_gates_per_wg != 1 && t->fft_gates_per_wg != 4 && t->fft_gates_per_wg != 8)
         return fail(CEMU_ERR_PARAM, "fft_gates_per_wg must be 1, 4 or 8");
+    if (t->int8_gates_per_wg != 0 && t->int8_gates_per_wg != 1 && t->int8_gates_per_wg != 16)
+        return fail(CEMU_ERR_PARAM, "int8_gates_per_wg must be 1 or 16 (0 selects 16)");
     std::lock_guard<std::mutex> lock(ck->mu);
     ck->tuning = *t;
+    if (ck->tuning.int8_gates_per_wg == 0) ck->tuning.int8_gates_per_wg = 16;
     return CEMU_OK;
 }
 

@@ -41,7 +41,7 @@ struct cemu_cloud_key {
     uint32_t *d_ext = nullptr;   // [cap][N+1] extracted samples
     int64_t ext_cap = 0;
     std::mutex mu;
-    cemu_tuning tuning = {8, 8, {0, 0, 0, 0, 0, 0}};
+    cemu_tuning tuning = {8, 8, 16, {0, 0, 0, 0, 0}};
     // Kernel timing (cemu_profile_enable): (kind, start, stop) event triples.
     mutable bool profiling = false;
     struct ProfileRec {

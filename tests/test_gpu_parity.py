@@ -136,6 +136,35 @@ def test_toy_all_gates_ragged_bit_exact(toy, dev):
     assert np.array_equal(lk.decrypt(out), want)
 
 
+def test_int8_latency_kernel_toy_bit_exact(toy, dev):
+    """The one-gate-per-workgroup int8 kernel (key limbs in the MFMA columns,
+    the gate's digit Toeplitz matrix as the other operand) against the exact
+    oracle: all ten gates x four input rows plus a ragged tail, both wave
+    counts; an empty batch and a single gate."""
+    lk, ok = toy
+    ops, a, b = W.all_gates_rows()
+    ops = np.concatenate([ops, ops[:3]])
+    a = np.concatenate([a, a[:3]])
+    b = np.concatenate([b, b[:3]])
+    c1 = lk.encrypt(a, seed=61)
+    c2 = lk.encrypt(b, seed=62)
+    oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
+    saved = cemu.get_tuning(lk)
+    try:
+        for waves in (8, 4):
+            say(f"[gpu] toy int8 latency kernel, {waves} waves, B = {len(ops)}")
+            cemu.set_tuning(lk, int8_waves=waves, int8_gates_per_wg=1)
+            ext, out = run_gates(lk, ops, c1, c2, dev, form="int8")
+            assert np.array_equal(ext, oext)
+            assert np.array_equal(out, oout)
+            ext1, out1 = run_gates(lk, ops[:1], c1[:1], c2[:1], dev, form="int8")
+            assert np.array_equal(ext1, oext[:1]) and np.array_equal(out1, oout[:1])
+            ext0, out0 = run_gates(lk, ops[:0], c1[:0], c2[:0], dev, form="int8")
+            assert ext0.shape[0] == 0 and out0.shape[0] == 0
+    finally:
+        cemu.set_tuning(lk, **saved)
+
+
 def test_std_batch_sampled_bit_exact(std, dev):
     """Standard parameters, 4096-gate batch in the launch configuration of the
     benchmark; every decryption exact, sampled gates bit-exact vs. oracle."""
@@ -366,7 +395,11 @@ def test_tuning_variants_give_identical_results(std, dev):
     try:
         for form, tun in [("fft64", {"fft_gates_per_wg": 8}), ("fft64", {"fft_gates_per_wg": 4}),
                           ("fft64", {"fft_gates_per_wg": 1}),
-                          ("int8", {"int8_waves": 8}), ("int8", {"int8_waves": 4})]:
+                          ("int8", {"int8_waves": 8, "int8_gates_per_wg": 16}),
+                          ("int8", {"int8_waves": 4, "int8_gates_per_wg": 16}),
+                          ("int8", {"int8_waves": 8, "int8_gates_per_wg": 1}),
+                          ("int8", {"int8_waves": 4, "int8_gates_per_wg": 1})]:
+            say(f"[gpu] tuning variant {form} {tun}")
             cemu.set_tuning(lk, **tun)
             ext, out = run_gates(lk, ops, c1, c2, dev, form=form)
             if ref is None:
@@ -376,6 +409,8 @@ def test_tuning_variants_give_identical_results(std, dev):
             cemu.set_tuning(lk, int8_waves=6)
         with pytest.raises(cemu.CemuError):
             cemu.set_tuning(lk, fft_gates_per_wg=2)
+        with pytest.raises(cemu.CemuError):
+            cemu.set_tuning(lk, int8_gates_per_wg=2)
     finally:
         cemu.set_tuning(lk, **saved)
     oext, _ = O.bootstrap_batch(ok, ops[:4].astype(np.int32), c1[:4], c2[:4], want_out=False)
