@@ -269,7 +269,10 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
 // operand is the negacyclic Toeplitz matrix of the gate's own digit row,
 //   T_p[m][k] = E_p[m - k],  E_p[s] = d_p[s] (s >= 0), -d_p[s + N] (s < 0),
 // kept in LDS as X_p[v] = E_p[v - N], v in [0, 2N) (digits are int8, so the
-// negated half is exact), and the B operand holds the key: column
+// negated half is exact). X is stored four times, copy r shifted down by r
+// bytes, so a lane whose 16-byte window starts at byte s reads four whole
+// dwords from copy s & 3 and forms its fragment without byte alignment
+// instructions. The B operand holds the key: column
 // n = 4 q + kappa (n < 8) is limb kappa of BK_i[p][q], columns 8..15 are
 // zero. One 16x16x64 MFMA thus produces every limb of both outputs; the
 // limbs are recombined across the four lanes of a quad (shift by 8 kappa,
@@ -288,42 +291,34 @@ struct LatShape {
     static constexpr int MT = N / 32;               // 16-row M-tiles per wave (N/2 rows)
     static constexpr int KT = N / 64 / KS;          // 64-wide K-tiles per wave and digit row
     static constexpr int NDELTA = MT + 4 * (KT - 1);
-    static constexpr int XROW = 2 * N + 16;         // bytes per extended digit row, + read slack
+    static constexpr int XD = N / 2;                // dwords per extended digit row X_p
+    static constexpr int XCOPY = BR_ROWS * XD + 8;  // dwords per shifted copy; +8 staggers the copies' banks
     static_assert(WAVES == 4 || WAVES == 8, "waves");
     static_assert(KT >= 1 && MT >= 1, "shape");
 };
 
 // acc[a] += T_tile(a, b) * B_tile(b) for the wave's K-tiles b; fragment di
-// serves the pairs with a - 4 b = di - 4 (KT - 1) and sits 16 bytes above
-// fragment di - 1.
+// serves the pairs with a - 4 b = di - 4 (KT - 1) and is the four dwords at
+// pr[4 di .. 4 di + 3] of the lane's shifted copy.
 template <int N, int WAVES>
-__device__ __forceinline__ void lat_mfma_block(const uint32_t *__restrict__ pr, uint32_t shift,
-                                               v4i (&acc)[LatShape<N, WAVES>::MT],
+__device__ __forceinline__ void lat_mfma_block(const uint32_t *__restrict__ pr, v4i (&acc)[LatShape<N, WAVES>::MT],
                                                const v4i (&bf)[LatShape<N, WAVES>::KT])
 {
     using S = LatShape<N, WAVES>;
-    uint32_t w0 = pr[0], w1 = pr[1], w2 = pr[2], w3 = pr[3], w4 = pr[4];
+    // Software pipeline: fragment di + 1 is requested before the MFMAs of
+    // fragment di are issued; sched_barrier keeps that order.
+    v4i fr = v4i{(int)pr[0], (int)pr[1], (int)pr[2], (int)pr[3]};
     static_for<0, S::NDELTA>([&](auto dI) {
         constexpr int di = decltype(dI)::value;
-        const v4i fr = v4i{(int)__builtin_amdgcn_alignbyte(w1, w0, shift), (int)__builtin_amdgcn_alignbyte(w2, w1, shift),
-                           (int)__builtin_amdgcn_alignbyte(w3, w2, shift), (int)__builtin_amdgcn_alignbyte(w4, w3, shift)};
-        uint32_t n1 = 0, n2 = 0, n3 = 0, n4 = 0;
-        if constexpr (di + 1 < S::NDELTA) {
-            n1 = pr[4 * di + 5];
-            n2 = pr[4 * di + 6];
-            n3 = pr[4 * di + 7];
-            n4 = pr[4 * di + 8];
-        }
+        v4i nx = fr;
+        if constexpr (di + 1 < S::NDELTA)
+            nx = v4i{(int)pr[4 * di + 4], (int)pr[4 * di + 5], (int)pr[4 * di + 6], (int)pr[4 * di + 7]};
         static_for<0, S::KT>([&](auto bI) {
             constexpr int b = decltype(bI)::value;
             constexpr int a = di - 4 * (S::KT - 1) + 4 * b;
             if constexpr (a >= 0 && a < S::MT) acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[a], 0, 0, 0);
         });
-        w0 = w4;
-        w1 = n1;
-        w2 = n2;
-        w3 = n3;
-        w4 = n4;
+        fr = nx;
         __builtin_amdgcn_sched_barrier(0);
     });
 }
@@ -335,7 +330,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
 {
     using S = LatShape<N, WAVES>;
     __shared__ __attribute__((aligned(16))) uint32_t acc_s[2][N];
-    __shared__ __attribute__((aligned(16))) uint32_t xs[BR_ROWS][S::XROW / 4];
+    __shared__ __attribute__((aligned(16))) uint32_t xs[4 * S::XCOPY];   // copy r, row p, dword w
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int ks = wave % S::KS, mh = (wave / S::KS) & 1, c = wave / (2 * S::KS);
@@ -351,11 +346,10 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
         acc_s[1][m] = tt < (uint32_t)N ? 0x20000000u : 0xE0000000u;
     }
 
-    // A fragment source of this lane (byte offset in X_p, 1 <= s0 and the
-    // last fragment ends at byte 2N - 1).
+    // A fragment source of this lane: byte offset s0 in X_p (1 <= s0, and the
+    // last fragment ends at byte 2N - 1), read as dword s0 / 4 of copy s0 & 3.
     const int s0 = N + 16 * S::MT * mh - 64 * S::KT * ks + col - 16 * g4 - 15 - 64 * (S::KT - 1);
-    const uint32_t frag_shift = (uint32_t)(s0 & 3);
-    const int frag_dw = s0 >> 2;
+    const uint32_t *xsrc = xs + (s0 & 3) * S::XCOPY + (s0 >> 2);
 
     // B fragments: limb kappa of BK_i[p][q] for k in the lane's 16-byte group,
     // read reversed from the key (byte N - 16 - k0 - 16 g4 .. + 15); columns
@@ -377,26 +371,47 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
     for (int i = 0; i < n; ++i) {
         const uint32_t a = bar[i];
         __syncthreads();   // ACC of the previous step complete; X consumed
-        // Extended digit rows of D = X^a ACC_c - ACC_c, four coefficients per item.
+        // Extended digit rows of D = X^a ACC_c - ACC_c. Item (c, k4) owns
+        // coefficients 4 k4 .. 4 k4 + 3, i.e. dword k4 (negated digits) and
+        // dword N/4 + k4 (digits) of X_p; it also takes the digits of the next
+        // group, which the shifted copies of those dwords reach into.
         for (int e = tid; e < N / 2; e += S::THREADS) {
             const int cc = e / (N / 4), k4 = e - cc * (N / 4);
-            const u4 own = *reinterpret_cast<const u4 *>(&acc_s[cc][4 * k4]);
-            const uint32_t un[4] = {own.x, own.y, own.z, own.w};
-            uint32_t word[3] = {0u, 0u, 0u};
+            const bool last = k4 + 1 == N / 4;
+            uint32_t word[2][3];   // digit fields + 64 of groups k4 and k4 + 1 (mod N/4), one byte each
+            static_for<0, 2>([&](auto hI) {
+                constexpr int h = decltype(hI)::value;
+                const int kg = h == 0 ? k4 : (last ? 0 : k4 + 1);
+                const u4 own = *reinterpret_cast<const u4 *>(&acc_s[cc][4 * kg]);
+                const uint32_t un[4] = {own.x, own.y, own.z, own.w};
+                word[h][0] = word[h][1] = word[h][2] = 0u;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const uint32_t tt = ((uint32_t)(4 * k4 + t) - a) & (uint32_t)(2 * N - 1);
-                uint32_t v = acc_s[cc][tt & (uint32_t)(N - 1)];
-                v = (tt & (uint32_t)N) ? 0u - v : v;
-                const uint32_t y = v - un[t] + kDigitOffset;
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t tt = ((uint32_t)(4 * kg + t) - a) & (uint32_t)(2 * N - 1);
+                    uint32_t v = acc_s[cc][tt & (uint32_t)(N - 1)];
+                    v = (tt & (uint32_t)N) ? 0u - v : v;
+                    const uint32_t y = v - un[t] + kDigitOffset;
 #pragma unroll
-                for (int j = 0; j < 3; ++j) word[j] |= ((y >> (32 - 7 * (j + 1))) & 127u) << (8 * t);
-            }
+                    for (int j = 0; j < 3; ++j) word[h][j] |= ((y >> (32 - 7 * (j + 1))) & 127u) << (8 * t);
+                }
+            });
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 // bytes f = d + 64 in [0, 128): d = (f + 64) ^ 0x80, -d = (0xC0 - f) ^ 0x80, no carries
-                xs[3 * cc + j][N / 4 + k4] = (word[j] + 0x40404040u) ^ 0x80808080u;
-                xs[3 * cc + j][k4] = (0xC0C0C0C0u - word[j]) ^ 0x80808080u;
+                const uint32_t pos_lo = (word[0][j] + 0x40404040u) ^ 0x80808080u;
+                const uint32_t neg_lo = (0xC0C0C0C0u - word[0][j]) ^ 0x80808080u;
+                const uint32_t pos_hi = (word[1][j] + 0x40404040u) ^ 0x80808080u;
+                const uint32_t neg_hi = (0xC0C0C0C0u - word[1][j]) ^ 0x80808080u;
+                // the dword after the negated half's last one is the first of the
+                // digit half; nothing is read past the digit half's last byte
+                const uint32_t next_neg = last ? pos_hi : neg_hi;
+                const uint32_t next_pos = last ? 0u : pos_hi;
+                uint32_t *row = xs + (3 * cc + j) * S::XD;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    row[r * S::XCOPY + k4] = r == 0 ? neg_lo : __builtin_amdgcn_alignbyte(next_neg, neg_lo, (uint32_t)r);
+                    row[r * S::XCOPY + N / 4 + k4] = r == 0 ? pos_lo : __builtin_amdgcn_alignbyte(next_pos, pos_lo, (uint32_t)r);
+                }
             }
         }
         __syncthreads();   // digit rows visible, every read of ACC done
@@ -410,7 +425,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
             // next (step, row); past the last step reload step 0 (unused)
             const int ni = j < 2 ? i : (i + 1 < n ? i + 1 : 0);
             load_b(ni, 3 * c + (j < 2 ? j + 1 : 0), nb);
-            lat_mfma_block<N, WAVES>(&xs[3 * c + j][frag_dw], frag_shift, acc, bf);
+            lat_mfma_block<N, WAVES>(xsrc + (3 * c + j) * S::XD, acc, bf);
         }
         // Delta_q[m] = sum_kappa 2^(8 kappa) C[m][4 q + kappa]: the four limbs
         // of an output row sit in the four lanes of a quad (lanes 4q .. 4q+3 of
