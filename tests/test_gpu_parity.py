@@ -418,13 +418,17 @@ def test_tuning_variants_give_identical_results(std, dev):
 
 
 def test_autotuner_picks_and_caches(std, dev, tmp_path):
-    from paper_2101_03403_amd.autotune import Autotuner, bucket
+    from paper_2101_03403_amd.autotune import CANDIDATES, Autotuner, bucket
     lk, _ = std
     path = str(tmp_path / "tune.json")
     t = Autotuner(lk, cache_path=path, reps=1)
     form, tun = t.best(100)
     assert bucket(100) == 128 and form in ("fft64", "int8")
-    assert len(t.measurements[128]) == 5
+    assert len(t.measurements[128]) == len(CANDIDATES)
+    # restricted to one form, only that form's shapes are measured
+    ti = Autotuner(lk, forms=("int8",), reps=1)
+    assert ti.best(20)[0] == "int8"
+    assert len(ti.measurements[32]) == sum(1 for f, _ in CANDIDATES if f == "int8")
     t2 = Autotuner(lk, cache_path=path)
     assert t2.best(120) == (form, tun)      # same bucket, from the file, no measuring
     assert t2.measurements == {}
