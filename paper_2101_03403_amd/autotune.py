@@ -110,7 +110,11 @@ class Autotuner:
             self.table[b] = (form, tun)
             self._save()
         form, tun = self.table[b]
-        return form, json.loads(tun) if isinstance(tun, str) else tun
+        tun = dict(json.loads(tun) if isinstance(tun, str) else tun)
+        if form == "int8":
+            # a cached choice written before the one-gate shape existed means the 16-gate shape
+            tun.setdefault("int8_gates_per_wg", 16)
+        return form, tun
 
     def apply(self, B: int) -> str:
         """Set the key's tuning for a batch of B gates; returns the form."""

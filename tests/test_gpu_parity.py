@@ -165,6 +165,41 @@ def test_int8_latency_kernel_toy_bit_exact(toy, dev):
         cemu.set_tuning(lk, **saved)
 
 
+def test_int8_latency_kernel_std_rounds_and_mux(std, dev):
+    """Standard parameters: the one-gate-per-workgroup int8 kernel on a batch
+    of 300 gates (more workgroups than one per compute unit, so they run in
+    rounds) and on a MUX level (two blind rotations per MUX) equals the
+    16-gate int8 kernel word for word; decryptions exact; sampled gates and
+    MUXes bit-exact against the oracle."""
+    lk, ok = std
+    B = 300
+    ops, a, b = W.gate_batch(B, seed=71)
+    c1 = lk.encrypt(a, seed=72)
+    c2 = lk.encrypt(b, seed=72, first_index=B)
+    bits, cts = _mux_inputs(lk, 40, 73)
+    saved = cemu.get_tuning(lk)
+    res = {}
+    try:
+        for shape in (16, 1):
+            say(f"[gpu] std int8, {shape} gate(s) per workgroup, B = {B} gates + 40 MUXes")
+            cemu.set_tuning(lk, int8_waves=8, int8_gates_per_wg=shape)
+            res[shape] = (run_gates(lk, ops, c1, c2, dev, form="int8"), _run_mux(lk, cts, dev, "int8"))
+    finally:
+        cemu.set_tuning(lk, **saved)
+    (ext16, out16), mux16 = res[16]
+    (ext1, out1), mux1 = res[1]
+    assert np.array_equal(ext1, ext16) and np.array_equal(out1, out16) and np.array_equal(mux1, mux16)
+    truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
+    want = np.array([truth[int(o)](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
+    assert np.array_equal(lk.decrypt(out1), want)
+    assert np.array_equal(lk.decrypt(mux1), np.where(bits[0] == 1, bits[1], bits[2]))
+    idx = W.sample_indices(B, 4, seed=74)
+    oext, oout = O.bootstrap_batch(ok, ops[idx].astype(np.int32), c1[idx], c2[idx])
+    assert np.array_equal(ext1[idx], oext) and np.array_equal(out1[idx], oout)
+    midx = W.sample_indices(40, 3, seed=75)
+    assert np.array_equal(mux1[midx], O.mux_batch(ok, cts[0][midx], cts[1][midx], cts[2][midx]))
+
+
 def test_std_batch_sampled_bit_exact(std, dev):
     """Standard parameters, 4096-gate batch in the launch configuration of the
     benchmark; every decryption exact, sampled gates bit-exact vs. oracle."""
