@@ -276,9 +276,10 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
 // n = 4 q + kappa (n < 8) is limb kappa of BK_i[p][q], columns 8..15 are
 // zero. One 16x16x64 MFMA thus produces every limb of both outputs; the
 // limbs are recombined across the four lanes of a quad (shift by 8 kappa,
-// two DPP adds) and each wave adds its share into ACC with LDS integer
-// atomics, which wrap modulo 2^32 like the sum itself, so the order of the
-// adds does not matter and the result is bit-exact. Inside a lane's 16-byte
+// then a reduce-scatter with two DPP exchanges that leaves each lane one
+// full row) and each wave adds its share into ACC with LDS integer atomics,
+// which wrap modulo 2^32 like the sum itself, so the order of the adds does
+// not matter and the result is bit-exact. Inside a lane's 16-byte
 // group the k order is reversed in both operands (k = k0 + 16 g + 15 - t for
 // byte t), which turns the key's reversed storage (BK[m] at byte N - 1 - m)
 // into one aligned 16-byte load per K-tile and leaves X in natural order.
