@@ -60,10 +60,11 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 TRAFFIC = {
     "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "f4e3779f4670c50b",
               "bytes": 486_963 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
-    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "9d3cada7d3eac37b",
-             "bytes": 245_920 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
-    "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "f79207ee4fcb2cb6",
-           "bytes": 361_598 * 1024 * 2 + 10_183 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "2f8f16a9c2448ccf",
+             "bytes": 245_908 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
+    # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
+    "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "8f9eb8b89663227d",
+           "bytes": (274 + 398_147) * 1024 * 2 + (10_096 + 29_152) * 1024, "batch": 4096},
 }
 
 
@@ -486,7 +487,8 @@ def key_switch_report(prof, B):
     avg = ms / cnt
     sec = avg * 1e-3
     hbm = traffic_bytes("ks", B)
-    return {"kernel": "ks_mfma_kernel<1024, false>", "avg_ms": avg,
+    return {"kernel": "ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)" if B == 4096
+            else "ks_mfma_kernel<1024, SPLIT>", "avg_ms": avg,
             "int8_TOPs": KS_OPS_PER_GATE * B / sec / 1e12, "frac_int8_peak": KS_OPS_PER_GATE * B / sec / PEAK_INT8_OPS,
             "hbm_bytes": hbm, "hbm_GBps": hbm / sec / 1e9 if hbm else None,
             "frac_hbm_peak": hbm / sec / PEAK_HBM_BYTES if hbm else None,
