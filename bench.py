@@ -373,16 +373,19 @@ def emulator_while_loop(keys, dev, form, count=42, tuner=None, prefix="gates"):
             "form": form if tuner is None else "autotuned per level width"}
 
 
-def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None, prefix="gates"):
+def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None, prefix="gates", pack=None):
     """1024 independent instructions (40 % ADD/SUB, 20 % 8x8/16x16 array MUL,
     20 % LT/EQ, 20 % AND/OR/XOR; widths 8/16/32), gates of each level merged
-    across instructions into one launch. Makespan of one warm run."""
+    across instructions into one launch. Makespan of one warm run. With
+    ``pack`` the levels are refilled to whole rounds of that many blind
+    rotations within each gate's slack (circuits.pack_levels); without it
+    every gate runs at its earliest level."""
     import torch
     from paper_2101_03403_amd import circuits as Cc, workloads as W
 
     mix = W.instruction_mix(count, seed)
     cs = [Cc.instruction_circuit(k, w, prefix=prefix) for k, w, _, _ in mix]
-    prog = Cc.Program(cs).to_device(dev)
+    prog = Cc.Program(cs, pack=pack).to_device(dev)
     bits = []
     for k, w, a, b in mix:
         bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
@@ -410,7 +413,21 @@ def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None, prefix="gat
             "bootstraps_per_s": prog.num_bootstraps() / (ms * 1e-3), "decrypt_exact": f"{ok}/{count}",
             "level_width_histogram": hist,
             "prefix": {"gates": "the paper's AND/OR o operator", "mux": "one MUX per o carry"}[prefix],
-            "form": form if tuner is None else "autotuned per level width"}
+            "form": form if tuner is None else "autotuned per level width",
+            "schedule": (f"levels refilled to whole rounds of {pack} blind rotations within each gate's slack"
+                         if pack else "every gate at its earliest level")}
+
+
+def mixed_stream_both(keys, dev, form, tuner=None, prefix="gates"):
+    """The mixed stream with levels filled to whole rounds of the throughput
+    kernel (8 gates per compute unit), and the earliest-level schedule beside it."""
+    import torch
+    rnd = 8 * torch.cuda.get_device_properties(dev).multi_processor_count
+    rec = mixed_stream(keys, dev, form, tuner=tuner, prefix=prefix, pack=rnd)
+    asap = mixed_stream(keys, dev, form, tuner=tuner, prefix=prefix)
+    rec["earliest_level_schedule"] = {k: asap[k] for k in ("makespan_ms", "bootstraps_per_s", "levels",
+                                                           "decrypt_exact", "level_width_histogram")}
+    return rec
 
 
 FFT_KERNEL = {8: "br_fft_kernel<8>", 4: "br_fft_kernel<4>", 1: "br_fft_lat_kernel"}
@@ -574,8 +591,8 @@ def main():
                                     for b, c in sorted(tuner_i8.table.items())}
     rec_sub = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, kind="SUB")
     rec_sub_mux = None if args.no_add else add32_latency(keys, dev, args.form, tuner=tuner, prefix="mux", kind="SUB")
-    rec_mix = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner)
-    rec_mix_mux = None if args.no_mixed else mixed_stream(keys, dev, args.form, tuner=tuner, prefix="mux")
+    rec_mix = None if args.no_mixed else mixed_stream_both(keys, dev, args.form, tuner=tuner)
+    rec_mix_mux = None if args.no_mixed else mixed_stream_both(keys, dev, args.form, tuner=tuner, prefix="mux")
     rec_shift = None if args.no_shift else shift32_latency(keys, dev, args.form, tuner=tuner)
     rec_seq = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner)
     rec_seq_mux = None if args.no_seq else sequential_units(keys, dev, args.form, tuner=tuner, prefix="mux")

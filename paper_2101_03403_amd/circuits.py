@@ -500,17 +500,103 @@ class Level:
         return int(self.mux[0].shape[0])
 
 
+def pack_levels(circuits: list, round_size: int) -> list:
+    """Level assignment for a merged program that fills whole launch rounds.
+
+    Every bootstrapped node (gate: one blind rotation, MUX: two) keeps its
+    circuit's level as the earliest it may run and gets a latest level from
+    the program's depth D (the depth does not grow). Levels are then filled
+    in order: the nodes whose latest level has come must run; the other ready
+    nodes, most urgent first, join them until the level's blind rotations
+    reach the next multiple of ``round_size`` (one full round of the
+    throughput kernel: every workgroup busy), or one round when nothing is
+    due. NOT runs at its input's level, inputs and constants at 0. Returns
+    one level list per circuit, in the form of ``Circuit.lv``."""
+    boot_kinds = ("gate", "mux")
+    depth = max((c.depth() for c in circuits), default=0)
+    # global ids of bootstrapped nodes; a wire's producer is the bootstrapped
+    # node behind it (through NOTs), or -1 for inputs and constants
+    gid, lo, hi, cost, preds = [], [], [], [], []
+    producer = []
+    for c in circuits:
+        prod = [-1] * len(c.nodes)
+        bound = [depth] * len(c.nodes)
+        ids = [-1] * len(c.nodes)
+        for w, (kind, op, a, b) in enumerate(c.nodes):
+            if kind == "not":
+                prod[w] = prod[a]
+            elif kind in boot_kinds:
+                ids[w] = len(lo)
+                prod[w] = ids[w]
+                lo.append(c.lv[w])
+                hi.append(depth)
+                cost.append(1 if kind == "gate" else 2)
+                ins = (op, a, b) if kind == "mux" else (a, b)
+                preds.append([prod[x] for x in ins])
+        # latest levels, in reverse topological order (nodes are stored in
+        # creation order, inputs before their consumers)
+        for w in range(len(c.nodes) - 1, -1, -1):
+            kind, op, a, b = c.nodes[w]
+            if kind in boot_kinds:
+                h = bound[w]
+                hi[ids[w]] = h
+                for x in ((op, a, b) if kind == "mux" else (a, b)):
+                    bound[x] = min(bound[x], h - 1)
+            elif kind == "not":
+                bound[a] = min(bound[a], bound[w])
+        gid.append(ids)
+        producer.append(prod)
+    nb = len(lo)
+    lo = np.asarray(lo, np.int64)
+    hi = np.asarray(hi, np.int64)
+    cost = np.asarray(cost, np.int64)
+    pm = np.full((nb, 3), -1, np.int64)
+    for i, ps in enumerate(preds):
+        pm[i, :len(ps)] = ps
+    lev = np.zeros(nb + 1, np.int64)          # lev[-1] (no producer) stays 0
+    for L in range(1, depth + 1):
+        pl = lev[pm]                            # levels of the producers (0: unscheduled or none)
+        done = (pl < L) & ((pl > 0) | (pm < 0))
+        ready = (lev[:nb] == 0) & (lo <= L) & done.all(axis=1)
+        due = ready & (hi == L)
+        m = int(cost[due].sum())
+        cap = round_size * max(1, -(-m // round_size))
+        take = due.copy()
+        opt = np.flatnonzero(ready & ~due)
+        if opt.size and m < cap:
+            opt = opt[np.argsort(hi[opt], kind="stable")]
+            room = cap - m
+            csum = np.cumsum(cost[opt])
+            take[opt[csum <= room]] = True
+        lev[:nb][take] = L
+    assert nb == 0 or lev[:nb].min() >= 1, "every bootstrapped node gets a level"
+    out = []
+    for c, ids, prod in zip(circuits, gid, producer):
+        lv = [0] * len(c.nodes)
+        for w, (kind, op, a, b) in enumerate(c.nodes):
+            if kind in boot_kinds:
+                lv[w] = int(lev[ids[w]])
+            elif kind == "not":
+                lv[w] = lv[a]
+        out.append(lv)
+    return out
+
+
 class Program:
     """Many circuit instances merged level by level into batched launches.
 
     Pool layout: every wire of every instance gets one row of a device
     ciphertext pool [rows][n+1]; instance k's wire w is row offset[k] + w.
+    With ``pack`` (blind rotations per full launch round) the levels are
+    reassigned by :func:`pack_levels`; otherwise each node keeps its
+    circuit's level.
     """
 
-    def __init__(self, circuits: list):
+    def __init__(self, circuits: list, pack: int | None = None):
         self.circuits = circuits
         self.offsets = np.cumsum([0] + [len(c.nodes) for c in circuits])
         self.rows = int(self.offsets[-1])
+        lvs = pack_levels(circuits, pack) if pack else [c.lv for c in circuits]
         per_level = {}
         per_level_mux = {}
         nots = {}
@@ -518,7 +604,7 @@ class Program:
         for k, c in enumerate(circuits):
             off = int(self.offsets[k])
             for w, (kind, op, a, b) in enumerate(c.nodes):
-                L = c.lv[w]
+                L = lvs[k][w]
                 if kind == "gate":
                     per_level.setdefault(L, []).append((op, off + a, off + b, off + w))
                 elif kind == "mux":

@@ -73,6 +73,56 @@ def test_program_merges_levels_across_instances():
         produced |= set(L.io.tolist())
 
 
+def _run_program_plain(prog, in_bits):
+    """Execute a Program level by level on cleartext bits, in the order the
+    device runs it (NOTs of level L-1, then level L's gates and MUXes)."""
+    v = np.zeros(prog.rows, np.int64)
+    v[prog.input_rows] = np.asarray(in_bits, np.int64)
+    v[prog.consts[1]] = prog.consts[0]
+    for L in prog.levels:
+        src, dst = L.nots
+        v[dst] = 1 - v[src]
+        for op, a, b, o in zip(L.ops, L.ia, L.ib, L.io):
+            v[o] = C._PLAIN[int(op)](int(v[a]), int(v[b]))
+        ms, ma, mb, mo = L.mux
+        v[mo] = np.where(v[ms] == 1, v[ma], v[mb])
+    src, dst = prog.tail_nots
+    v[dst] = 1 - v[src]
+    return v
+
+
+@pytest.mark.parametrize("prefix", ["gates", "mux"])
+def test_packed_program_fills_rounds_and_computes_the_same(prefix):
+    """Levels reassigned to fill whole launch rounds: same depth and the same
+    gates, every level's blind rotations a multiple of the round size until
+    the last levels, every input produced before its consumer, and level by
+    level cleartext execution gives every instruction's integer result."""
+    mix = W.instruction_mix(96, seed=11)
+    cs = [C.instruction_circuit(k, w, prefix=prefix) for k, w, _, _ in mix]
+    bits = []
+    for k, w, a, b in mix:
+        bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
+    plain = C.Program(cs)
+    R = 64
+    packed = C.Program(cs, pack=R)
+    assert packed.depth == plain.depth
+    assert packed.num_gates() == plain.num_gates() and packed.num_muxes() == plain.num_muxes()
+    boot = [w + 2 * m for w, m in zip(packed.level_widths(), packed.level_mux_counts())]
+    full = [b % R == 0 for b in boot]
+    assert sum(full) >= len(boot) - 3, boot          # only the last levels may be ragged
+    produced = set(packed.input_rows.tolist()) | set(packed.consts[1].tolist())
+    for L in packed.levels:
+        produced |= set(L.nots[1].tolist())
+        for x in (L.ia, L.ib) + L.mux[:3]:
+            assert set(x.tolist()) <= produced
+        produced |= set(L.io.tolist()) | set(L.mux[3].tolist())
+    for prog in (plain, packed):
+        v = _run_program_plain(prog, bits)
+        for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
+            got = C.bits_to_int([int(x) for x in v[np.array(c.outputs["out"]) + off]])
+            assert got == C.instruction_result(k, w, a, b), (k, w, a, b)
+
+
 def test_mixed_stream_recipe():
     mix = W.instruction_mix(1000, seed=5)
     kinds = [k for k, *_ in mix]
