@@ -315,11 +315,12 @@ def to_i32(x):
     return x.astype(np.int64) - ((x >> 31).astype(np.int64) << 32)
 
 
-@pytest.mark.parametrize("B,fg", [(37, 8), (512, 8), (37, 1), (300, 1)])
+@pytest.mark.parametrize("B,fg", [(37, 8), (512, 8), (4096, 8), (37, 1), (300, 1)])
 def test_fft_form_decrypts_and_phase_error(std, dev, B, fg):
     """FP64-FFT form (fg = gates per workgroup; 1 is the latency kernel):
     every decryption exact; extracted samples compared with the oracle on
-    sampled gates (raw words and decrypted phase)."""
+    sampled gates (raw words and decrypted phase). B = 4096 at 8 gates per
+    workgroup is the benchmark's batch in its launch shape (two full rounds)."""
     lk, ok = std
     say(f"[gpu] fft64 form B={B} fft_gates_per_wg={fg}")
     ops, a, b = W.gate_batch(B, seed=51 + B)
