@@ -868,6 +868,31 @@ def test_batches_beyond_one_grid_pass(std, dev):
         cemu.set_tuning(lk, **saved)
 
 
+def test_int8_round_tail_split(std, dev):
+    """The 16-gate int8 kernel also runs in rounds of 16 gates per CU; a short
+    tail behind full rounds launches on the one-gate kernel. Batches sized from
+    the device's CU count (a small and a long tail, and one just past the
+    limit) equal, word for word, the one-gate kernel's output for the whole
+    batch; every decryption is exact."""
+    lk, _ = std
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    saved = cemu.get_tuning(lk)
+    try:
+        for B in (16 * cus + 37, 16 * cus + 6 * cus, 16 * cus + 6 * cus + 1):
+            say(f"[gpu] int8 tail split: B={B} (CUs {cus})")
+            ops, a, b = W.gate_batch(B, seed=400 + B)
+            c1 = lk.encrypt(a, seed=401)
+            c2 = lk.encrypt(b, seed=401, first_index=B)
+            cemu.set_tuning(lk, int8_waves=8, int8_gates_per_wg=16)
+            _, got = run_gates(lk, ops, c1, c2, dev, form="int8", want_ext=False)
+            cemu.set_tuning(lk, int8_waves=8, int8_gates_per_wg=1)
+            _, ref = run_gates(lk, ops, c1, c2, dev, form="int8", want_ext=False)
+            assert np.array_equal(got, ref)
+            assert np.array_equal(lk.decrypt(got), _plain_gates(ops, a, b))
+    finally:
+        cemu.set_tuning(lk, **saved)
+
+
 def test_fft_round_tail_split(std, dev):
     """Every FFT shape runs one workgroup per CU, so a batch of k full rounds
     plus a short tail launches the tail separately on a smaller shape (the
