@@ -168,7 +168,13 @@ def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample, add32=True):
     t0 = time.time()
     O.bootstrap_batch(okeys, ops[:1].astype(np.int32), c1[:1], c2[:1], want_extracted=False)
     one_gate = time.time() - t0
-    res = {"value": sample / dt, "unit": "gates/s", "cores": cores, "kind": "oracle",
+    cpu_model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu_model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    res = {"value": sample / dt, "unit": "gates/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model,
            "sample": f"first {sample} gates of the same 4096-gate batch, same keys and ciphertexts; "
                      f"exact schoolbook products, OpenMP across gates; {dt:.1f} s "
                      f"(oracle keygen {t_keygen:.1f} s not timed)",
