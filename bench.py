@@ -64,7 +64,7 @@ TRAFFIC = {
              "bytes": 245_640 * 1024 * 2 + 17_936 * 1024, "batch": 4096},
     # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
     "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "8f9eb8b89663227d",
-           "bytes": (274 + 398_147) * 1024 * 2 + (10_096 + 29_152) * 1024, "batch": 4096},
+           "bytes": (274 + 396_562) * 1024 * 2 + (10_096 + 29_152) * 1024, "batch": 4096},
 }
 
 
