@@ -59,7 +59,7 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 # reported as null.
 TRAFFIC = {
     "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "f4e3779f4670c50b",
-              "bytes": 486_963 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
+              "bytes": 486_918 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
     "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "12d75da0bf62b236",
              "bytes": 245_640 * 1024 * 2 + 17_936 * 1024, "batch": 4096},
     # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
