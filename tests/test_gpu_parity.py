@@ -415,6 +415,34 @@ def test_program_int8_form_small(std, dev):
         assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
 
 
+@pytest.mark.parametrize("prefix", ["gates", "mux"])
+def test_packed_program_equals_earliest_level_schedule(toy, dev, prefix):
+    """A mixed stream of 64 instructions with its levels refilled to whole
+    rounds of 64 blind rotations (pack_levels) writes, word for word, the same
+    ciphertext pool as the earliest-level schedule (a gate's bootstrap does
+    not depend on the batch it runs in), and every instruction decrypts to
+    its integer result (toy parameters, int8 form)."""
+    from paper_2101_03403_amd import circuits as Cc
+    lk, _ = toy
+    mix = W.instruction_mix(64, seed=17)
+    cs = [Cc.instruction_circuit(k, w, prefix=prefix) for k, w, _, _ in mix]
+    bits = []
+    for k, w, a, b in mix:
+        bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
+    pools = []
+    for pack in (None, 64):
+        prog = Cc.Program(cs, pack=pack).to_device(dev)
+        say(f"[gpu] mixed {prefix} pack={pack}: {prog.depth} levels, widths {prog.level_widths()[:6]}...")
+        pool = _program_pool(prog, lk, bits, dev)
+        prog.run(lk, pool, form="int8")
+        torch.cuda.synchronize()
+        pools.append(to_host_u32(pool))
+    assert np.array_equal(pools[0], pools[1])
+    for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
+        got = Cc.bits_to_int(lk.decrypt(pools[1][np.array(c.outputs["out"]) + off]))
+        assert got == Cc.instruction_result(k, w, a, b), (k, w, a, b, got)
+
+
 def test_tuning_variants_give_identical_results(std, dev):
     """Every launch configuration the autotuner may pick computes the same
     ciphertexts (ragged batch of 45 gates). The FFT64 latency kernel sums in
