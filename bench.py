@@ -115,39 +115,39 @@ def parse():
     return ap.parse_args()
 
 
+def expected_word(kind, width, a, b):
+    """Integer result an instruction circuit must decrypt to: W-bit wrap for
+    ADD / SUB / bitwise / shifts (amount mod W), 2W bits for the multipliers,
+    one bit for LT / EQ, 2^W - 1 for a division by zero."""
+    M = 1 << width
+    sgn = lambda v: v - M if v >> (width - 1) else v  # noqa: E731
+    if kind in ("LLS", "LRS", "ARS"):
+        k = b % width
+        return {"LLS": (a << k) % M, "LRS": a >> k, "ARS": (sgn(a) >> k) % M}[kind]
+    if kind == "DIV":
+        return a // b if b else M - 1
+    if kind == "SMULSEQ":
+        return (sgn(a) * sgn(b)) % (M * M)
+    return {"ADD": (a + b) % M, "SUB": (a - b) % M, "MUL": a * b, "MULSEQ": a * b, "LT": int(a < b),
+            "EQ": int(a == b), "AND": a & b, "OR": a | b, "XOR": a ^ b}[kind]
+
+
 def cpu_add32_latency(okeys, seed=404):
-    """One 32-bit ADD (the paper's AND/OR prefix, 12 levels) through the CPU
-    oracle, level by level: each level's gates in one batch, OpenMP across
-    them (the level structure of the paper's own parallel ADD, Sec. 5.2).
-    Returns (seconds, decrypted sum correct)."""
+    """One 32-bit ADD (the paper's AND/OR prefix, 12 levels) as the oracle's
+    own netlist of Sec. 5.2 on the oracle's gates, level by level: each
+    level's gates in one batch, OpenMP across them (the level structure of the
+    paper's own parallel ADD). Returns (seconds, decrypted sum correct)."""
+    from oracle import circuits as OC
     from oracle import oracle as O
-    from paper_2101_03403_amd import circuits as Cc
     rng = np.random.default_rng(seed)
     a, b = (int(x) for x in rng.integers(0, 1 << 32, 2, dtype=np.uint64))
-    c = Cc.adder_instance(32)
-    prog = Cc.Program([c])
-    n = okeys.params.n
-    pool = np.zeros((prog.rows, n + 1), np.uint32)
-    bits = np.asarray(Cc.int_to_bits(a, 32) + Cc.int_to_bits(b, 32), np.uint8)
-    pool[prog.input_rows] = O.encrypt_bits(okeys, bits, seed=seed)
-    for bit, row in zip(prog.consts[0], prog.consts[1]):
-        pool[row] = 0
-        pool[row, n] = 0x20000000 if bit else 0xE0000000
+    net = OC.instruction("ADD", 32)
+    inputs = O.encrypt_bits(okeys, np.asarray(OC.to_bits(a, 32) + OC.to_bits(b, 32), np.uint8), seed=seed)
     t0 = time.time()
-    for L in prog.levels:
-        src, dst = L.nots
-        pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
-        if L.ops.shape[0]:
-            _, out = O.bootstrap_batch(okeys, L.ops.astype(np.int32), pool[L.ia], pool[L.ib], want_extracted=False)
-            pool[L.io] = out
-        if L.num_muxes:
-            ms, ma, mb, mo = L.mux
-            pool[mo] = O.mux_batch(okeys, pool[ms], pool[ma], pool[mb])
-    src, dst = prog.tail_nots
-    pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
+    ct = net.run_encrypted(okeys, inputs)
     dt = time.time() - t0
-    got = Cc.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[np.array(c.outputs["sum"])]))
-    return dt, got == Cc.instruction_result("ADD", 32, a, b)
+    got = OC.from_bits(O.decrypt_bits(okeys.lwe_key, np.stack([ct[w] for w in net.outputs["out"]])))
+    return dt, got == OC.word_result("ADD", 32, a, b)
 
 
 def cpu_baseline(keys_seed, ops, c1, c2, gpu_out, sample, add32=True):
@@ -279,7 +279,7 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="ga
         ok = 0
         for k, (a, b) in enumerate(ops):
             rows = np.array(cs[k].outputs["sum" if kind == "ADD" else "diff"]) + prog.offsets[k]
-            ok += int(Cc.bits_to_int(keys.decrypt(host[rows])) == Cc.instruction_result(kind, 32, int(a), int(b)))
+            ok += int(Cc.bits_to_int(keys.decrypt(host[rows])) == expected_word(kind, 32, int(a), int(b)))
         ms = float(np.median(times))
         key = "batch" if inst == instances else "single"
         out[key] = {"instances": inst, "latency_ms": ms, "amortized_ms_per_instruction": ms / inst,
@@ -327,7 +327,7 @@ def shift32_latency(keys, dev, form, reps=3, tuner=None):
         got = Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"])]))
         out[mode] = {"latency_ms": float(np.median(times)), "muxes": prog.num_muxes(),
                      "bootstraps": prog.num_bootstraps(), "levels": prog.depth,
-                     "decrypt_exact": int(got == Cc.instruction_result(mode, 32, a, amt))}
+                     "decrypt_exact": int(got == expected_word(mode, 32, a, amt))}
     out["form"] = form if tuner is None else "autotuned per launch width"
     out["timing"] = "hipGraph of the 5 MUX levels, median of 3 replays (hip events)"
     return out
@@ -371,7 +371,7 @@ def sequential_units(keys, dev, form, width=32, reps=2, tuner=None, prefix="gate
         host = pool.cpu().numpy().view(np.uint32)
         got = Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"])]))
         out[kind] = {"latency_ms": float(np.median(times)), "gates": prog.num_gates(), "muxes": prog.num_muxes(),
-                     "levels": prog.depth, "decrypt_exact": int(got == Cc.instruction_result(kind, width, a, b))}
+                     "levels": prog.depth, "decrypt_exact": int(got == expected_word(kind, width, a, b))}
     out["width"] = width
     out["prefix"] = {"gates": "the paper's AND/OR o operator", "mux": "one MUX per o carry"}[prefix]
     out["form"] = form if tuner is None else "autotuned per level width"
@@ -439,7 +439,7 @@ def mixed_stream(keys, dev, form, count=1024, seed=2021, tuner=None, prefix="gat
     ok = 0
     for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
         ok += int(Cc.bits_to_int(keys.decrypt(host[np.array(c.outputs["out"]) + off])) ==
-                  Cc.instruction_result(k, w, a, b))
+                  expected_word(k, w, a, b))
     widths = np.array(prog.level_widths())
     hist = {f"<{lim}": int(np.sum(widths < lim)) for lim in (256, 1024, 4096, 16384)}
     hist[">=16384"] = int(np.sum(widths >= 16384))

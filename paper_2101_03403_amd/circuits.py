@@ -48,14 +48,6 @@ from . import cemu
 
 NAND, AND, OR, XOR, XNOR, NOR, ANDNY, ANDYN, ORNY, ORYN = range(10)
 
-_PLAIN = {
-    NAND: lambda a, b: 1 - (a & b), AND: lambda a, b: a & b, OR: lambda a, b: a | b,
-    XOR: lambda a, b: a ^ b, XNOR: lambda a, b: 1 - (a ^ b), NOR: lambda a, b: 1 - (a | b),
-    ANDNY: lambda a, b: (1 - a) & b, ANDYN: lambda a, b: a & (1 - b),
-    ORNY: lambda a, b: (1 - a) | b, ORYN: lambda a, b: a | (1 - b),
-}
-
-
 @dataclass
 class Circuit:
     """A DAG over wires. Kinds: 'in', 'gate' (bootstrapped), 'mux' (FHE MUX,
@@ -96,24 +88,6 @@ class Circuit:
 
     def const(self, bit: int) -> int:
         return self._new("const", int(bit))
-
-    # ---------------------------------------------------------- evaluation
-    def eval_plain(self, in_bits) -> np.ndarray:
-        """Evaluate on cleartext bits (for structure tests)."""
-        vals = np.zeros(len(self.nodes), np.int64)
-        it = iter(in_bits)
-        for w, (kind, op, a, b) in enumerate(self.nodes):
-            if kind == "in":
-                vals[w] = next(it)
-            elif kind == "gate":
-                vals[w] = _PLAIN[op](int(vals[a]), int(vals[b]))
-            elif kind == "mux":
-                vals[w] = vals[a] if vals[op] else vals[b]
-            elif kind == "not":
-                vals[w] = 1 - vals[a]
-            else:
-                vals[w] = op
-        return vals
 
     def levels(self) -> np.ndarray:
         return np.array(self.lv, dtype=np.int64)
@@ -748,19 +722,6 @@ def flag_setting_circuit(kind: str, width: int, prefix: str = PREFIX_GATES) -> C
     return c
 
 
-def nzcv_reference(kind: str, width: int, a: int, b: int) -> list:
-    """Cleartext [N, Z, C, V] of ADDS / SUBS / CMP on W-bit operands."""
-    m = (1 << width) - 1
-    sa = a - (1 << width) if a >> (width - 1) else a
-    sb = b - (1 << width) if b >> (width - 1) else b
-    if kind == "ADDS":
-        r, cflag, sr = (a + b) & m, int(a + b > m), sa + sb
-    else:
-        r, cflag, sr = (a - b) & m, int(a >= b), sa - sb
-    vflag = int(sr < -(1 << (width - 1)) or sr >= (1 << (width - 1)))
-    return [r >> (width - 1), int(r == 0), cflag, vflag]
-
-
 def instruction_circuit(kind: str, width: int, prefix: str = PREFIX_GATES) -> Circuit:
     """One instruction as a circuit with inputs a, b (width bits each, LSB
     first) and output 'out'. Shifts (LLS / LRS / ARS) are register mode: b is
@@ -794,24 +755,3 @@ def instruction_circuit(kind: str, width: int, prefix: str = PREFIX_GATES) -> Ci
         raise ValueError(f"unknown instruction {kind}")
     c.outputs["out"] = out
     return c
-
-
-def instruction_result(kind: str, width: int, a: int, b: int) -> int:
-    """Cleartext result the circuit must decrypt to."""
-    m = (1 << width) - 1
-    if kind in (LLS, LRS, ARS):
-        k = b % width
-        if kind == LLS:
-            return (a << k) & m
-        if kind == LRS:
-            return a >> k
-        signed = a - (1 << width) if a >> (width - 1) else a
-        return (signed >> k) & m
-    if kind == "SMULSEQ":
-        sa = a - (1 << width) if a >> (width - 1) else a
-        sb = b - (1 << width) if b >> (width - 1) else b
-        return (sa * sb) % (1 << (2 * width))
-    if kind == "DIV":
-        return a // b if b else m
-    return {"ADD": (a + b) & m, "SUB": (a - b) & m, "MUL": a * b, "MULSEQ": a * b, "LT": int(a < b),
-            "EQ": int(a == b), "AND": a & b, "OR": a | b, "XOR": a ^ b, "ORN": (a | (~b & m)) & m}[kind]

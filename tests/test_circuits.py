@@ -11,8 +11,10 @@ oracle (toy parameters) and decrypted.
 import numpy as np
 import pytest
 
+from oracle import circuits as OC
 from paper_2101_03403_amd import circuits as C
 from paper_2101_03403_amd import workloads as W
+from plainsim import eval_dag, run_program_plain
 
 
 def test_adder_levels_match_paper_32():
@@ -41,8 +43,8 @@ def test_add_sub_cleartext(width):
     for a, b in vals:
         a, b = int(a), int(b)
         bits = C.int_to_bits(a, width) + C.int_to_bits(b, width)
-        assert C.bits_to_int(add.eval_plain(bits)[add.outputs["sum"]]) == (a + b) % (1 << width)
-        assert C.bits_to_int(sub.eval_plain(bits)[sub.outputs["diff"]]) == (a - b) % (1 << width)
+        assert C.bits_to_int(eval_dag(add, bits)[add.outputs["sum"]]) == (a + b) % (1 << width)
+        assert C.bits_to_int(eval_dag(sub, bits)[sub.outputs["diff"]]) == (a - b) % (1 << width)
 
 
 @pytest.mark.parametrize("kind", W.MIX_KINDS)
@@ -54,8 +56,8 @@ def test_instruction_circuits_cleartext(kind, width):
         a, b = (int(x) for x in rng.integers(0, 1 << width, 2, dtype=np.uint64))
         if kind in ("LT", "EQ") and rng.random() < 0.3:
             b = a
-        v = c.eval_plain(C.int_to_bits(a, width) + C.int_to_bits(b, width))
-        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, width, a, b)
+        v = eval_dag(c, C.int_to_bits(a, width) + C.int_to_bits(b, width))
+        assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result(kind, width, a, b)
 
 
 def test_program_merges_levels_across_instances():
@@ -71,24 +73,6 @@ def test_program_merges_levels_across_instances():
         produced |= set(L.nots[1].tolist())
         assert set(L.ia.tolist()) <= produced and set(L.ib.tolist()) <= produced
         produced |= set(L.io.tolist())
-
-
-def _run_program_plain(prog, in_bits):
-    """Execute a Program level by level on cleartext bits, in the order the
-    device runs it (NOTs of level L-1, then level L's gates and MUXes)."""
-    v = np.zeros(prog.rows, np.int64)
-    v[prog.input_rows] = np.asarray(in_bits, np.int64)
-    v[prog.consts[1]] = prog.consts[0]
-    for L in prog.levels:
-        src, dst = L.nots
-        v[dst] = 1 - v[src]
-        for op, a, b, o in zip(L.ops, L.ia, L.ib, L.io):
-            v[o] = C._PLAIN[int(op)](int(v[a]), int(v[b]))
-        ms, ma, mb, mo = L.mux
-        v[mo] = np.where(v[ms] == 1, v[ma], v[mb])
-    src, dst = prog.tail_nots
-    v[dst] = 1 - v[src]
-    return v
 
 
 @pytest.mark.parametrize("prefix", ["gates", "mux"])
@@ -117,10 +101,10 @@ def test_packed_program_fills_rounds_and_computes_the_same(prefix):
             assert set(x.tolist()) <= produced
         produced |= set(L.io.tolist()) | set(L.mux[3].tolist())
     for prog in (plain, packed):
-        v = _run_program_plain(prog, bits)
+        v = run_program_plain(prog, bits)
         for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
             got = C.bits_to_int([int(x) for x in v[np.array(c.outputs["out"]) + off]])
-            assert got == C.instruction_result(k, w, a, b), (k, w, a, b)
+            assert got == OC.word_result(k, w, a, b), (k, w, a, b)
 
 
 def test_mixed_stream_recipe():
@@ -171,7 +155,7 @@ def test_small_circuits_under_fhe_with_oracle():
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
-        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
 
 
 # ------------------------------------------------------------------ shifters (Sec. 5.4)
@@ -185,8 +169,8 @@ def test_barrel_shift_cleartext(mode, width):
         a = int(rng.integers(0, 1 << width, dtype=np.uint64))
         if k % 3 == 0:
             a |= 1 << (width - 1)                     # exercise the sign fill of ARS
-        v = c.eval_plain(C.int_to_bits(a, width) + C.int_to_bits(k, width))
-        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(mode, width, a, k), (a, k)
+        v = eval_dag(c, C.int_to_bits(a, width) + C.int_to_bits(k, width))
+        assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result(mode, width, a, k), (a, k)
 
 
 def test_barrel_shift_structure_32():
@@ -210,8 +194,8 @@ def test_shift_immediate_cleartext(mode):
         out = C.shift_immediate(c, A, k, mode)
         assert c.num_bootstraps() == 0
         a = int(rng.integers(0, 1 << 16)) | (1 << 15) * (k % 2)
-        v = c.eval_plain(C.int_to_bits(a, 16))
-        assert C.bits_to_int(v[out]) == C.instruction_result(mode, 16, a, k)
+        v = eval_dag(c, C.int_to_bits(a, 16))
+        assert C.bits_to_int(v[out]) == OC.word_result(mode, 16, a, k)
 
 
 def test_shifters_under_fhe_with_oracle():
@@ -229,7 +213,7 @@ def test_shifters_under_fhe_with_oracle():
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
-        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
 
 
 # ------------------------------------------------------------------ multiplier and divider (Sec. 5.5, 5.6)
@@ -241,8 +225,8 @@ def test_sequential_units_exhaustive_4bit(kind):
     c = C.instruction_circuit(kind, 4)
     for a in range(16):
         for b in range(16):
-            v = c.eval_plain(C.int_to_bits(a, 4) + C.int_to_bits(b, 4))
-            assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, 4, a, b), (a, b)
+            v = eval_dag(c, C.int_to_bits(a, 4) + C.int_to_bits(b, 4))
+            assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result(kind, 4, a, b), (a, b)
 
 
 @pytest.mark.parametrize("kind", SEQ_KINDS)
@@ -255,8 +239,8 @@ def test_sequential_units_cleartext(kind, width):
     cases += [tuple(int(x) for x in rng.integers(0, 1 << width, 2, dtype=np.uint64)) for _ in range(25)]
     cases += [(int(rng.integers(0, 1 << width, dtype=np.uint64)), int(rng.integers(1, 1 << (width // 2)))) for _ in range(10)]
     for a, b in cases:
-        v = c.eval_plain(C.int_to_bits(a, width) + C.int_to_bits(b, width))
-        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, width, a, b), (a, b)
+        v = eval_dag(c, C.int_to_bits(a, width) + C.int_to_bits(b, width))
+        assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result(kind, width, a, b), (a, b)
 
 
 def test_sequential_units_structure():
@@ -282,7 +266,7 @@ def test_add_with_carry_wire_cleartext():
         rng = np.random.default_rng(w)
         for _ in range(40):
             a, b, ci = int(rng.integers(0, 1 << w)), int(rng.integers(0, 1 << w)), int(rng.integers(0, 2))
-            v = c.eval_plain(C.int_to_bits(a, w) + C.int_to_bits(b, w) + [ci])
+            v = eval_dag(c, C.int_to_bits(a, w) + C.int_to_bits(b, w) + [ci])
             assert C.bits_to_int(v[s]) + (int(v[cout]) << w) == a + b + ci
 
 
@@ -301,7 +285,7 @@ def test_sequential_units_under_fhe_with_oracle():
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
-        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
 
 
 
@@ -318,11 +302,11 @@ def test_mux_prefix_units_exhaustive(width):
         for b in range(1 << width):
             bits = C.int_to_bits(a, width) + C.int_to_bits(b, width)
             for k, c in cs.items():
-                v = c.eval_plain(bits)
-                assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(k, width, a, b), (k, a, b)
+                v = eval_dag(c, bits)
+                assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result(k, width, a, b), (k, a, b)
             for k, c in fl.items():
-                v = c.eval_plain(bits)
-                assert [int(x) for x in v[c.outputs["nzcv"]]] == C.nzcv_reference(k, width, a, b), (k, a, b)
+                v = eval_dag(c, bits)
+                assert [int(x) for x in v[c.outputs["nzcv"]]] == OC.nzcv(k, width, a, b), (k, a, b)
 
 
 @pytest.mark.parametrize("kind", ["ADD", "SUB", "LT", "MULSEQ", "DIV"])
@@ -333,8 +317,8 @@ def test_mux_prefix_units_cleartext_32(kind):
     cases = [(m, m), (0, 0), (m, 1), (1 << 31, 1 << 31), (5, 0)]
     cases += [tuple(int(x) for x in rng.integers(0, 1 << 32, 2, dtype=np.uint64)) for _ in range(25)]
     for a, b in cases:
-        v = c.eval_plain(C.int_to_bits(a, 32) + C.int_to_bits(b, 32))
-        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result(kind, 32, a, b), (a, b)
+        v = eval_dag(c, C.int_to_bits(a, 32) + C.int_to_bits(b, 32))
+        assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result(kind, 32, a, b), (a, b)
 
 
 def test_mux_prefix_structure_32():
@@ -365,7 +349,7 @@ def test_mux_prefix_add_with_carry_wire_cleartext():
         rng = np.random.default_rng(w + 100)
         for _ in range(40):
             a, b, ci = int(rng.integers(0, 1 << w)), int(rng.integers(0, 1 << w)), int(rng.integers(0, 2))
-            v = c.eval_plain(C.int_to_bits(a, w) + C.int_to_bits(b, w) + [ci])
+            v = eval_dag(c, C.int_to_bits(a, w) + C.int_to_bits(b, w) + [ci])
             assert C.bits_to_int(v[s]) + (int(v[cout]) << w) == a + b + ci
 
 
@@ -386,4 +370,4 @@ def test_mux_prefix_under_fhe_with_oracle():
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
-        assert got == C.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)

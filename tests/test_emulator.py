@@ -1,13 +1,16 @@
 """Emulator front-end (Sec. 4, 6): assembler, condition codes, NZCV flag
 circuits on the CPU; whole programs on the GPU against a cleartext
-interpreter written here."""
+interpreter written here on the oracle's integer semantics (oracle.circuits:
+word_result, nzcv, condition)."""
 import itertools
 import sys
 
 import numpy as np
 import pytest
 
+from oracle import circuits as OC
 from paper_2101_03403_amd import circuits as C
+from plainsim import eval_dag
 from paper_2101_03403_amd import emulator as E
 
 WHILE_LOOP = """
@@ -54,12 +57,14 @@ def test_condition_codes_against_signed_unsigned_compare():
     """After CMP a, b the ARM conditions equal the integer comparisons."""
     w = 4
     for a, b in itertools.product(range(16), repeat=2):
-        n, z, c, v = C.nzcv_reference("CMP", w, a, b)
+        n, z, c, v = OC.nzcv("CMP", w, a, b)
         sa = a - 16 if a >= 8 else a
         sb = b - 16 if b >= 8 else b
         want = {"EQ": a == b, "NE": a != b, "CS": a >= b, "CC": a < b, "HI": a > b, "LS": a <= b,
                 "GE": sa >= sb, "LT": sa < sb, "GT": sa > sb, "LE": sa <= sb, "AL": True}
         for cond, val in want.items():
+            assert OC.condition(cond, n, z, c, v) == val, (a, b, cond)
+            # the client's branch decision in the product agrees
             assert E.condition_holds(cond, n, z, c, v) == val, (a, b, cond)
 
 
@@ -67,9 +72,9 @@ def test_condition_codes_against_signed_unsigned_compare():
 def test_flag_circuits_exhaustive_4bit(kind):
     c = C.flag_setting_circuit(kind, 4)
     for a, b in itertools.product(range(16), repeat=2):
-        v = c.eval_plain(C.int_to_bits(a, 4) + C.int_to_bits(b, 4))
-        assert [int(x) for x in v[c.outputs["nzcv"]]] == C.nzcv_reference(kind, 4, a, b)
-        assert C.bits_to_int(v[c.outputs["out"]]) == C.instruction_result("ADD" if kind == "ADDS" else "SUB", 4, a, b)
+        v = eval_dag(c, C.int_to_bits(a, 4) + C.int_to_bits(b, 4))
+        assert [int(x) for x in v[c.outputs["nzcv"]]] == OC.nzcv(kind, 4, a, b)
+        assert C.bits_to_int(v[c.outputs["out"]]) == OC.word_result("ADD" if kind == "ADDS" else "SUB", 4, a, b)
 
 
 def test_flag_circuits_32bit_random():
@@ -79,8 +84,8 @@ def test_flag_circuits_32bit_random():
         cases = [(0, 0), (2**31, 2**31), (2**31 - 1, 1), (5, 5), (0, 1)]
         cases += [tuple(int(x) for x in rng.integers(0, 2**32, 2, dtype=np.uint64)) for _ in range(30)]
         for a, b in cases:
-            v = c.eval_plain(C.int_to_bits(a, 32) + C.int_to_bits(b, 32))
-            assert [int(x) for x in v[c.outputs["nzcv"]]] == C.nzcv_reference(kind, 32, a, b), (kind, a, b)
+            v = eval_dag(c, C.int_to_bits(a, 32) + C.int_to_bits(b, 32))
+            assert [int(x) for x in v[c.outputs["nzcv"]]] == OC.nzcv(kind, 32, a, b), (kind, a, b)
 
 
 # ------------------------------------------------------------------ cleartext interpreter (test reference)
@@ -107,17 +112,17 @@ def interpret(text, width, mem, max_steps=10000):
         elif ins.op == "STORE":
             mem[ins.imm] = regs[ins.rd]
         elif ins.op == "B":
-            if E.condition_holds(ins.cond, *flags):
+            if OC.condition(ins.cond, *flags):
                 nxt = labels[ins.target]
         elif ins.op in E.FLAG_KINDS:
             kind = E.FLAG_KINDS[ins.op]
             a, b = regs[ins.rn], op2()
-            flags = tuple(C.nzcv_reference(kind, width, a, b))
+            flags = tuple(OC.nzcv(kind, width, a, b))
             if ins.op != "CMP":
-                regs[ins.rd] = C.instruction_result("ADD" if kind == "ADDS" else "SUB", width, a, b)
+                regs[ins.rd] = OC.word_result("ADD" if kind == "ADDS" else "SUB", width, a, b)
         else:
             kind = E.ALU_KINDS[ins.op]
-            regs[ins.rd] = C.instruction_result(kind, width, regs[ins.rn], op2()) & m
+            regs[ins.rd] = OC.word_result(kind, width, regs[ins.rn], op2()) & m
         pc = nxt
     return regs, mem, flags, steps
 

@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+from oracle import circuits as OC  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from paper_2101_03403_amd import cemu, workloads as W  # noqa: E402
 
@@ -376,7 +377,7 @@ def test_program_add_sub_levels_and_graph(std, dev):
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
-        assert got == Cc.instruction_result(k, w, a, b)
+        assert got == OC.word_result(k, w, a, b)
     rs = np.random.default_rng(5)
     for L in prog.levels:
         pick = rs.choice(L.ops.shape[0], 3, replace=False)
@@ -412,7 +413,7 @@ def test_program_int8_form_small(std, dev):
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
-        assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
 
 
 @pytest.mark.parametrize("prefix", ["gates", "mux"])
@@ -440,7 +441,7 @@ def test_packed_program_equals_earliest_level_schedule(toy, dev, prefix):
     assert np.array_equal(pools[0], pools[1])
     for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(pools[1][np.array(c.outputs["out"]) + off]))
-        assert got == Cc.instruction_result(k, w, a, b), (k, w, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, w, a, b, got)
 
 
 def test_tuning_variants_give_identical_results(std, dev):
@@ -596,7 +597,7 @@ def test_program_shifters_levels_and_graph(std, dev):
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
-        assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
     rs = np.random.default_rng(6)
     for L in prog.levels:
         ms, ma, mb, mo = L.mux
@@ -643,7 +644,7 @@ def test_program_sequential_multiplier_and_divider(std, dev):
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
-        assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
     rs = np.random.default_rng(8)
     for L in prog.levels[::8]:
         if L.ops.shape[0] == 0:
@@ -700,7 +701,7 @@ def test_bootstrap_level_matches_separate_calls(std, dev, form):
     assert torch.equal(dense, out_level[_t(perm.astype(np.int64), dev)])
     assert torch.equal(only_g, only_g_ref) and torch.equal(only_m, only_m_ref)
     host = to_host_u32(out_level)
-    want_g = np.array([Cc._PLAIN[int(o)](int(bits[a]), int(bits[b])) for o, a, b in zip(ops_h, ia_h, ib_h)])
+    want_g = np.array([OC.gate_plain(int(o), bits[a], bits[b]) for o, a, b in zip(ops_h, ia_h, ib_h)])
     want_m = np.where(bits[ms_h] == 1, bits[ma_h], bits[mb_h])
     assert np.array_equal(lk.decrypt(host[perm[:G]]), want_g)
     assert np.array_equal(lk.decrypt(host[perm[G:]]), want_m)
@@ -742,7 +743,7 @@ def test_program_mux_prefix_levels_and_graph(std, dev):
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
-        assert got == Cc.instruction_result(k, w, a, b), (k, a, b, got)
+        assert got == OC.word_result(k, w, a, b), (k, a, b, got)
     rs = np.random.default_rng(9)
     for L in prog.levels:
         if L.ops.shape[0]:
