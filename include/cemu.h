@@ -75,10 +75,14 @@ enum {
     CEMU_NUM_GATE_OPS = 10
 };
 
+/* Largest LWE dimension of the unbootstrapped row operations (NOT, COPY,
+ * CONSTANT), and of keys: the key switch computes the n + 1 output words of
+ * a sample in one workgroup pass of at most 768 columns. */
 #define CEMU_MAX_LWE_N 4096
+#define CEMU_MAX_KEY_N 767
 
 typedef struct cemu_params {
-    int32_t n;         /* LWE dimension of gate ciphertexts: 1..CEMU_MAX_LWE_N */
+    int32_t n;         /* LWE dimension of gate ciphertexts: 1..CEMU_MAX_KEY_N */
     int32_t N;         /* TRLWE ring degree: 512 or 1024                      */
     int32_t k;         /* TRLWE mask count: must be 1                        */
     int32_t l;         /* bootstrapping-key gadget length: must be 3          */
@@ -136,6 +140,24 @@ int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int
 
 /* Batched bootstrapped binary gates: lincomb + modulus switch + blind
  * rotation + sample extraction + key switching, for B independent gates.
+ * The paper evaluates each gate as one call of the TFHE library (Sec. 3,
+ * Table "TFHEbenchmark"; correctness f(a, b) = Dec(g(Enc a, Enc b)), Sec. 2)
+ * and does not spell out its steps; they are read as TFHE's gate
+ * bootstrapping, which the paper builds on:
+ *   1. c = (0, ..., 0, kappa) + w1 c1 + w2 c2 with the gate's constants
+ *      (NAND +1/8, -1, -1; AND -1/8, 1, 1; OR +1/8, 1, 1; XOR +1/4, 2, 2;
+ *      XNOR -1/4, -2, -2; NOR -1/8, -1, -1; ANDNY -1/8, -1, 1; ANDYN -1/8,
+ *      1, -1; ORNY +1/8, -1, 1; ORYN +1/8, 1, -1);
+ *   2. every word rescaled to Z/2N: nearest integer of x 2N / 2^32, ties up,
+ *      2N wrapping to 0;
+ *   3. blind rotation: ACC = (0, X^-bbar v) with v = sum_j (1/8) X^j, then
+ *      for each i with abar_i != 0, ACC += BK_i (external product)
+ *      (X^abar_i ACC - ACC), the difference decomposed into l = 3 signed
+ *      digits of Bgbit = 7 bits (rounded to 21 bits, ties up, digits in
+ *      [-64, 64));
+ *   4. sample extraction of coefficient 0: (A_0, -A_{N-1}, ..., -A_1, B_0);
+ *   5. key switching as cemu_key_switch.
+ * The output encrypts g(a, b) as +-1/8 under the LWE key.
  *   ops:      device uint8_t [B], gate op codes (CEMU_NAND .. CEMU_ORYN)
  *   pool_in:  device uint32_t [P_in][n+1], ciphertext pool read by the gates
  *   ia, ib:   device int32_t [B], row of the first / second input in pool_in
@@ -163,14 +185,23 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops,
                          const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out,
                          int64_t B, void *hip_stream);
 
-/* The same gates without the final key switch: writes the extracted
- * dimension-N samples. out_N: device uint32_t [B][N+1]. Errors as
- * cemu_bootstrap_gates. */
+/* The same gates without the final key switch (steps 1-4 above): writes
+ * the extracted dimension-N samples, which encrypt +-1/8 under the TRLWE
+ * key's coefficients. This is the half of a gate that TFHE's MUX runs twice
+ * before one key switch (Table "TFHEbenchmark": MUX).
+ * out_N: device uint32_t [B][N+1]. Errors as cemu_bootstrap_gates. */
 int cemu_blind_rotate_extract(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
                               const int32_t *ia, const int32_t *ib, uint32_t *out_N, int64_t B,
                               void *hip_stream);
 
-/* Key switching of B dimension-N samples to dimension n.
+/* Key switching of B dimension-N samples to dimension n (the last step of
+ * a bootstrapped gate; the paper uses it inside the TFHE gate call, Sec. 3).
+ * Read as TFHE's key switch: each mask word a'_i is rounded to t * basebit
+ * bits (16 in the standard set: add 2^15 and truncate; no rounding when
+ * t * basebit = 32), split into t unsigned base-4 digits d_ij,
+ * most significant first, and the output is (0, ..., 0, b') minus the rows
+ * KS[i][j][d_ij] of the key-switching key, a row with digit 0 subtracting
+ * nothing. The phase is preserved up to the key's noise and the rounding.
  * in_N: device [B][N+1]; out_n: device [B][n+1]. Errors: CEMU_ERR_NULL,
  * CEMU_ERR_ALIGN, CEMU_ERR_RANGE (B < 0 or B > 2^40), CEMU_ERR_HIP. */
 int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *out_n, int64_t B,

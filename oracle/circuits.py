@@ -66,6 +66,20 @@ def gate_plain(op: int, a: int, b: int) -> int:
     return TRUTH[op][2 * int(a) + int(b)]
 
 
+def lwe_not(ct) -> np.ndarray:
+    """NOT without bootstrapping (Table "TFHEbenchmark": NOT): every word of
+    the sample negated mod 2^32, which negates the phase, +-1/8 -> -+1/8."""
+    return (np.uint32(0) - np.asarray(ct, np.uint32)).astype(np.uint32)
+
+
+def lwe_constant(bit: int, n: int) -> np.ndarray:
+    """CONSTANT (Table "TFHEbenchmark"): the noiseless trivial sample
+    (0, ..., 0, +1/8) for true, (0, ..., 0, -1/8) for false."""
+    c = np.zeros(n + 1, np.uint32)
+    c[n] = np.uint32(0x20000000 if bit else 0xE0000000)
+    return c
+
+
 class Netlist:
     """Nodes: ('in', k) | ('const', bit) | ('not', x) | ('gate', op, x, y) |
     ('mux', s, x, y) with mux = s ? x : y. Inputs and constants sit at level
@@ -158,11 +172,9 @@ class Netlist:
             if nd[0] == "in":
                 ct[w] = inputs[nd[1]].copy()
             elif nd[0] == "const":
-                c = np.zeros(n + 1, np.uint32)
-                c[n] = np.uint32(0x20000000 if nd[1] else 0xE0000000)
-                ct[w] = c
+                ct[w] = lwe_constant(nd[1], n)
             elif nd[0] == "not":
-                ct[w] = (np.uint32(0) - settle(nd[1])).astype(np.uint32)
+                ct[w] = lwe_not(settle(nd[1]))
             else:
                 raise RuntimeError("bootstrapped node used before its level ran")
             return ct[w]

@@ -4,7 +4,11 @@ For a cloud key and a batch size it measures every candidate launch
 configuration -- product form (FP64-FFT or int8-MFMA) x its tile choice
 (FFT: 8 or 4 gates per workgroup, or the one-gate-per-workgroup latency
 kernel; int8: 16 gates or one gate per workgroup, 8 or 4 waves) -- on a
-synthetic batch of that size, keeps the fastest, and caches the choice per
+seeded batch of that size that looks like real work (random bits encrypted
+under the key, gate types uniform over NAND / AND / OR / XOR, so the
+rescaled masks and the digits are uniform as in use; an all-zero batch would
+skip every blind-rotation step and time nothing), keeps the fastest, and
+caches the choice per
 (parameter set, batch-size bucket) in memory and optionally in a JSON file.
 Kernel timing uses the library's own HIP-event profiling (cemu_profile_*),
 so it measures exactly the blind-rotation + key-switch launches. The choice
@@ -21,6 +25,7 @@ import os
 import numpy as np
 
 from . import cemu
+from . import workloads as W
 
 CANDIDATES = (
     ("fft64", {"fft_gates_per_wg": 8}),
@@ -74,8 +79,11 @@ class Autotuner:
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         n = self.keys.n
-        pool = torch.zeros((2 * B, n + 1), dtype=torch.int32, device=dev)
-        ops = torch.zeros(B, dtype=torch.uint8, device=dev)
+        ops_h, a, b = W.gate_batch(B, seed=W.TUNE_SEED + B)
+        c1 = self.keys.encrypt(a, seed=W.TUNE_SEED)
+        c2 = self.keys.encrypt(b, seed=W.TUNE_SEED, first_index=B)
+        pool = torch.from_numpy(np.concatenate([c1, c2]).view(np.int32)).to(dev)
+        ops = torch.from_numpy(ops_h).to(dev)
         ia = torch.arange(B, dtype=torch.int32, device=dev)
         out = torch.zeros((B, n + 1), dtype=torch.int32, device=dev)
         saved = cemu.get_tuning(self.keys)

@@ -52,6 +52,8 @@ int check_params(const cemu_params *p)
     if (p->k != 1) return fail(CEMU_ERR_UNSUPPORTED, "only k = 1 is supported");
     if (p->N != 512 && p->N != 1024) return fail(CEMU_ERR_UNSUPPORTED, "N must be 512 or 1024");
     if (p->n < 1 || p->n > CEMU_MAX_LWE_N) return fail(CEMU_ERR_PARAM, "n must be in [1, 4096]");
+    if (p->n > CEMU_MAX_KEY_N)
+        return fail(CEMU_ERR_UNSUPPORTED, "keys need n <= 767 (the key switch writes n + 1 <= 768 columns)");
     if (p->l != 3 || p->bgbit != 7)
         return fail(CEMU_ERR_UNSUPPORTED, "the kernels need l = 3 and Bgbit = 7 (signed 7-bit digits)");
     if (p->basebit != 2) return fail(CEMU_ERR_UNSUPPORTED, "key switching needs basebit = 2");

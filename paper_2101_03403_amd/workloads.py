@@ -14,6 +14,7 @@ THROUGHPUT_OPS = (NAND, AND, OR, XOR)
 
 KEY_SEED = 0x2101_03403
 ENC_SEED = 0xC0FFEE
+TUNE_SEED = 0x7E57
 
 
 def gate_batch(B: int, seed: int, ops=THROUGHPUT_OPS):

@@ -14,6 +14,7 @@ import pytest
 from oracle import circuits as OC
 from paper_2101_03403_amd import circuits as C
 from paper_2101_03403_amd import workloads as W
+import oracle_program as OP
 from plainsim import eval_dag, run_program_plain
 
 
@@ -117,29 +118,6 @@ def test_mixed_stream_recipe():
     assert all(w in (8, 16) for k, w, *_ in mix if k == "MUL")
 
 
-def _run_with_oracle(prog, okeys, in_bits, enc_seed=3):
-    """Execute a Program level by level with the CPU oracle (test only)."""
-    from oracle import oracle as O
-    p = okeys.params
-    pool = np.zeros((prog.rows, p.n + 1), np.uint32)
-    pool[prog.input_rows] = O.encrypt_bits(okeys, np.asarray(in_bits, np.uint8), seed=enc_seed)
-    for bit, row in zip(prog.consts[0], prog.consts[1]):
-        pool[row] = 0
-        pool[row, p.n] = 0x20000000 if bit else 0xE0000000
-    for L in prog.levels:
-        src, dst = L.nots
-        pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
-        if L.ops.shape[0]:
-            _, out = O.bootstrap_batch(okeys, L.ops.astype(np.int32), pool[L.ia], pool[L.ib], want_extracted=False)
-            pool[L.io] = out
-        if L.num_muxes:
-            ms, ma, mb, mo = L.mux
-            pool[mo] = O.mux_batch(okeys, pool[ms], pool[ma], pool[mb])
-    src, dst = prog.tail_nots
-    pool[dst] = (0 - pool[src].astype(np.uint64)).astype(np.uint32)
-    return pool
-
-
 def test_small_circuits_under_fhe_with_oracle():
     """8-bit ADD and SUB plus a 4-bit EQ and LT, evaluated homomorphically
     gate by gate with the oracle (toy parameters), then decrypted."""
@@ -151,7 +129,13 @@ def test_small_circuits_under_fhe_with_oracle():
     bits = []
     for k, w, a, b in cases:
         bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
-    pool = _run_with_oracle(prog, okeys, bits)
+    pool0 = OP.oracle_pool(okeys, prog, bits, seed=3)
+    pool = OP.run_on_oracle(okeys, prog, pool0, range(len(cs)))
+    # replaying a subset of the instances writes the same rows
+    part = OP.run_on_oracle(okeys, prog, pool0, [1, 3])
+    rows = np.flatnonzero(OP.instance_rows(prog, [1, 3]))
+    assert np.array_equal(part[rows], pool[rows])
+    assert OP.bootstrapped_rows(prog, [1, 3]).size == cs[1].num_gates() + cs[3].num_gates()
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
@@ -209,7 +193,7 @@ def test_shifters_under_fhe_with_oracle():
     bits = []
     for k, w, a, b in cases:
         bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
-    pool = _run_with_oracle(prog, okeys, bits, enc_seed=8)
+    pool = OP.run_on_oracle(okeys, prog, OP.oracle_pool(okeys, prog, bits, seed=8), range(len(prog.circuits)))
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
@@ -281,7 +265,7 @@ def test_sequential_units_under_fhe_with_oracle():
     bits = []
     for k, w, a, b in cases:
         bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
-    pool = _run_with_oracle(prog, okeys, bits, enc_seed=9)
+    pool = OP.run_on_oracle(okeys, prog, OP.oracle_pool(okeys, prog, bits, seed=9), range(len(prog.circuits)))
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))
@@ -366,7 +350,7 @@ def test_mux_prefix_under_fhe_with_oracle():
     bits = []
     for k, w, a, b in cases:
         bits += C.int_to_bits(a, w) + C.int_to_bits(b, w)
-    pool = _run_with_oracle(prog, okeys, bits, enc_seed=10)
+    pool = OP.run_on_oracle(okeys, prog, OP.oracle_pool(okeys, prog, bits, seed=10), range(len(prog.circuits)))
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         rows = np.array(c.outputs["out"]) + off
         got = C.bits_to_int(O.decrypt_bits(okeys.lwe_key, pool[rows]))

@@ -19,6 +19,8 @@ from oracle import circuits as OC  # noqa: E402
 from oracle import oracle as O  # noqa: E402
 from paper_2101_03403_amd import cemu, workloads as W  # noqa: E402
 
+import oracle_program as OP  # noqa: E402  (tests/ helper)
+
 SEED = 20210108
 
 
@@ -107,8 +109,8 @@ def test_toy_eight_nand_bit_exact(toy, dev):
     lk, ok = toy
     say("[gpu] toy 8 NAND")
     ops, a, b = W.gate_batch(8, seed=11, ops=(W.NAND,))
-    c1 = lk.encrypt(a, seed=21)
-    c2 = lk.encrypt(b, seed=21, first_index=8)
+    c1 = O.encrypt_bits(ok, a, seed=21)
+    c2 = O.encrypt_bits(ok, b, seed=21, first_index=8)
     ext, out = run_gates(lk, ops, c1, c2, dev)
     oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
     assert np.array_equal(ext, oext)
@@ -124,8 +126,8 @@ def test_toy_all_gates_ragged_bit_exact(toy, dev):
     ops = np.concatenate([ops, ops[:3]])
     a = np.concatenate([a, a[:3]])
     b = np.concatenate([b, b[:3]])
-    c1 = lk.encrypt(a, seed=31)
-    c2 = lk.encrypt(b, seed=32)
+    c1 = O.encrypt_bits(ok, a, seed=31)
+    c2 = O.encrypt_bits(ok, b, seed=32)
     ext, out = run_gates(lk, ops, c1, c2, dev)
     oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
     assert np.array_equal(ext, oext)
@@ -147,8 +149,8 @@ def test_int8_latency_kernel_toy_bit_exact(toy, dev):
     ops = np.concatenate([ops, ops[:3]])
     a = np.concatenate([a, a[:3]])
     b = np.concatenate([b, b[:3]])
-    c1 = lk.encrypt(a, seed=61)
-    c2 = lk.encrypt(b, seed=62)
+    c1 = O.encrypt_bits(ok, a, seed=61)
+    c2 = O.encrypt_bits(ok, b, seed=62)
     oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
     saved = cemu.get_tuning(lk)
     try:
@@ -175,9 +177,9 @@ def test_int8_latency_kernel_std_rounds_and_mux(std, dev):
     lk, ok = std
     B = 300
     ops, a, b = W.gate_batch(B, seed=71)
-    c1 = lk.encrypt(a, seed=72)
-    c2 = lk.encrypt(b, seed=72, first_index=B)
-    bits, cts = _mux_inputs(lk, 40, 73)
+    c1 = O.encrypt_bits(ok, a, seed=72)
+    c2 = O.encrypt_bits(ok, b, seed=72, first_index=B)
+    bits, cts = _mux_inputs(ok, 40, 73)
     saved = cemu.get_tuning(lk)
     res = {}
     try:
@@ -201,33 +203,12 @@ def test_int8_latency_kernel_std_rounds_and_mux(std, dev):
     assert np.array_equal(mux1[midx], O.mux_batch(ok, cts[0][midx], cts[1][midx], cts[2][midx]))
 
 
-def test_std_batch_sampled_bit_exact(std, dev):
-    """Standard parameters, 4096-gate batch in the launch configuration of the
-    benchmark; every decryption exact, sampled gates bit-exact vs. oracle."""
-    lk, ok = std
-    B = 4096
-    say("[gpu] std 4096 batch")
-    ops, a, b = W.gate_batch(B, seed=41)
-    c1 = lk.encrypt(a, seed=W.ENC_SEED)
-    c2 = lk.encrypt(b, seed=W.ENC_SEED, first_index=B)
-    ext, out = run_gates(lk, ops, c1, c2, dev)
-    truth = {0: lambda x, y: 1 - (x & y), 1: lambda x, y: x & y, 2: lambda x, y: x | y, 3: lambda x, y: x ^ y}
-    want = np.array([truth[int(o)](int(x), int(y)) for o, x, y in zip(ops, a, b)], np.uint8)
-    assert np.array_equal(lk.decrypt(out), want)
-    assert np.array_equal(lk.decrypt_extracted(ext), want)
-    idx = W.sample_indices(B, 16, seed=42)
-    say(f"[gpu] oracle on {len(idx)} sampled gates")
-    oext, oout = O.bootstrap_batch(ok, ops[idx].astype(np.int32), c1[idx], c2[idx])
-    assert np.array_equal(ext[idx], oext)
-    assert np.array_equal(out[idx], oout)
-
-
-@pytest.mark.parametrize("B", [1, 37, 300, 1600])
+@pytest.mark.parametrize("B", [1, 37, 300, 1600, 4096])
 def test_key_switch_alone(std, dev, B):
     """Key switching alone, bit-exact against the oracle, across the launch
-    shapes: K split over 32 (B = 1, 37), 16 (300) and 4 (1600) workgroups per
-    tile with integer-atomic sums (B = 4096, unsplit, is covered by the gate
-    tests)."""
+    shapes: the K range split over 32 (B = 1, 37, 300), 8 (1600) and 2
+    (4096) workgroups per tile with integer-atomic sums. The unsplit launch
+    (B >= 6529) is covered at B = 8192 in test_gpu_full_parity."""
     lk, ok = std
     say(f"[gpu] key switch B={B}")
     rng = np.random.default_rng(7 + B)
@@ -245,7 +226,7 @@ def test_gather_scatter_pool(toy, dev):
     rng = np.random.default_rng(8)
     P = 20
     bits = rng.integers(0, 2, P).astype(np.uint8)
-    pool = lk.encrypt(bits, seed=9)
+    pool = O.encrypt_bits(ok, bits, seed=9)
     B = 17
     ia = rng.integers(0, P, B).astype(np.int32)
     ib = rng.integers(0, P, B).astype(np.int32)
@@ -267,8 +248,8 @@ def test_empty_and_single(toy, dev):
     cemu.bootstrap_gates(lk, torch.zeros(0, dtype=torch.uint8, device=dev), z, z, z,
                          torch.zeros((0, lk.n + 1), dtype=torch.int32, device=dev))
     ops = np.array([cemu.XOR], np.uint8)
-    c1 = lk.encrypt([1], seed=3)
-    c2 = lk.encrypt([1], seed=4)
+    c1 = O.encrypt_bits(ok, [1], seed=3)
+    c2 = O.encrypt_bits(ok, [1], seed=4)
     ext, out = run_gates(lk, ops, c1, c2, dev)
     oext, oout = O.bootstrap_batch(ok, ops.astype(np.int32), c1, c2)
     assert np.array_equal(out, oout)
@@ -276,9 +257,9 @@ def test_empty_and_single(toy, dev):
 
 
 def test_not_copy_constant(toy, dev):
-    lk, _ = toy
+    lk, ok = toy
     bits = np.array([0, 1, 1, 0], np.uint8)
-    c = lk.encrypt(bits, seed=13)
+    c = O.encrypt_bits(ok, bits, seed=13)
     dpool = to_dev(c, dev)
     idx = torch.arange(4, dtype=torch.int32, device=dev)
     dnot = torch.zeros_like(dpool)
@@ -295,7 +276,7 @@ def test_not_copy_constant(toy, dev):
 
 
 def test_errors_are_reported(toy, dev):
-    lk, _ = toy
+    lk, ok = toy
     z = torch.zeros(4, dtype=torch.int32, device=dev)
     # the FFT64 form is built for N = 1024 only: the toy set (N = 512) is refused
     ops = torch.zeros(2, dtype=torch.uint8, device=dev)
@@ -325,8 +306,8 @@ def test_fft_form_decrypts_and_phase_error(std, dev, B, fg):
     lk, ok = std
     say(f"[gpu] fft64 form B={B} fft_gates_per_wg={fg}")
     ops, a, b = W.gate_batch(B, seed=51 + B)
-    c1 = lk.encrypt(a, seed=61)
-    c2 = lk.encrypt(b, seed=61, first_index=B)
+    c1 = O.encrypt_bits(ok, a, seed=61)
+    c2 = O.encrypt_bits(ok, b, seed=61, first_index=B)
     saved = cemu.get_tuning(lk)
     try:
         cemu.set_tuning(lk, fft_gates_per_wg=fg)
@@ -344,22 +325,45 @@ def test_fft_form_decrypts_and_phase_error(std, dev, B, fg):
     werr = np.abs(to_i32(ext[idx].astype(np.int64) - oext.astype(np.int64))).max()
     say(f"[gpu] fft64 vs oracle: max |phase error| = {np.abs(perr).max()}, differing words = {words_diff}"
         f"/{oext.size}, max |word error| = {werr}")
-    assert np.abs(perr).max() < (1 << 20)
+    # every product is an integer polynomial rounded from double precision:
+    # while the transform error stays below one half, the extracted samples
+    # are the exact ones
+    assert words_diff == 0
 
 
-def _program_pool(prog, lk, bits, dev, seed=77):
-    pool = torch.zeros((prog.rows, lk.n + 1), dtype=torch.int32, device=dev)
-    enc = lk.encrypt(np.asarray(bits, np.uint8), seed=seed)
-    pool[torch.from_numpy(prog.input_rows.astype(np.int64)).to(dev)] = to_dev(enc, dev)
-    return pool
+def _program_pool(prog, ok, bits, dev, seed=77):
+    """Device pool holding the oracle's encryptions of the input bits, and
+    its host copy (the starting pool of the oracle's replay)."""
+    host0 = OP.oracle_pool(ok, prog, bits, seed)
+    return to_dev(host0, dev), host0
+
+
+def _check_against_oracle_replay(ok, prog, host0, host, instances, label, min_per_level=0):
+    """Replay the given instances on the oracle from the same encrypted
+    inputs (no GPU ciphertext enters the oracle) and require every row they
+    write to equal the GPU's word for word. Returns the per-level number of
+    compared blind-rotated outputs."""
+    want = OP.run_on_oracle(ok, prog, host0, instances, label=label)
+    mask = OP.instance_rows(prog, instances)
+    per_level = [int(mask[L.io].sum()) + int(mask[L.mux[3]].sum()) for L in prog.levels]
+    for li, L in enumerate(prog.levels):
+        width = int(L.io.shape[0]) + L.num_muxes
+        assert per_level[li] >= min(min_per_level, width), (li, per_level[li], width)
+    rows = np.flatnonzero(mask)
+    diff = int(np.sum(host[rows] != want[rows]))
+    say(f"[gpu] {label}: {int(sum(per_level))} bootstrapped outputs over {len(per_level)} levels "
+        f"(min {min(per_level) if per_level else 0} per level) against the oracle replay, differing words {diff}")
+    assert diff == 0
+    return per_level
 
 
 def test_program_add_sub_levels_and_graph(std, dev):
     """16 ADD32 + 16 SUB32 instances merged level by level (FFT64 form):
-    decryptions equal uint32 arithmetic; at every level 3 sampled gates are
-    bit-exact against the oracle on the GPU's own level inputs; a captured
-    hipGraph replayed 3 times (outputs cleared eagerly in between) reproduces
-    the eager pool exactly."""
+    decryptions equal uint32 arithmetic; two ADD and two SUB instances (at
+    least 64 gates of every level) replayed on the oracle from the same
+    encrypted inputs equal the GPU's pool word for word; a captured hipGraph
+    replayed 3 times (outputs cleared eagerly in between) reproduces the
+    eager pool exactly."""
     from paper_2101_03403_amd import circuits as Cc
     lk, ok = std
     rng = np.random.default_rng(123)
@@ -371,19 +375,14 @@ def test_program_add_sub_levels_and_graph(std, dev):
     for k, w, a, b in cases:
         bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
     say(f"[gpu] program: {prog.num_gates()} gates in {prog.depth} levels")
-    pool = _program_pool(prog, lk, bits, dev)
+    pool, host0 = _program_pool(prog, ok, bits, dev)
     prog.run(lk, pool, form="fft64")
     torch.cuda.synchronize()
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
         assert got == OC.word_result(k, w, a, b)
-    rs = np.random.default_rng(5)
-    for L in prog.levels:
-        pick = rs.choice(L.ops.shape[0], 3, replace=False)
-        _, oout = O.bootstrap_batch(ok, L.ops[pick].astype(np.int32), host[L.ia[pick]], host[L.ib[pick]],
-                                    want_extracted=False)
-        assert np.array_equal(host[L.io[pick]], oout)
+    _check_against_oracle_replay(ok, prog, host0, host, [0, 1, 16, 17], "ADD/SUB replay", min_per_level=64)
     # graph capture and replay
     eager = host.copy()
     g = prog.capture(lk, pool, form="fft64")
@@ -407,13 +406,14 @@ def test_program_int8_form_small(std, dev):
     bits = []
     for k, w, a, b in cases:
         bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
-    pool = _program_pool(prog, lk, bits, dev)
+    pool, host0 = _program_pool(prog, ok, bits, dev)
     prog.run(lk, pool, form="int8")
     torch.cuda.synchronize()
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
         assert got == OC.word_result(k, w, a, b), (k, a, b, got)
+    _check_against_oracle_replay(ok, prog, host0, host, [1, 3, 4, 5], "small int8 program replay")
 
 
 @pytest.mark.parametrize("prefix", ["gates", "mux"])
@@ -424,7 +424,7 @@ def test_packed_program_equals_earliest_level_schedule(toy, dev, prefix):
     not depend on the batch it runs in), and every instruction decrypts to
     its integer result (toy parameters, int8 form)."""
     from paper_2101_03403_amd import circuits as Cc
-    lk, _ = toy
+    lk, ok = toy
     mix = W.instruction_mix(64, seed=17)
     cs = [Cc.instruction_circuit(k, w, prefix=prefix) for k, w, _, _ in mix]
     bits = []
@@ -434,7 +434,7 @@ def test_packed_program_equals_earliest_level_schedule(toy, dev, prefix):
     for pack in (None, 64):
         prog = Cc.Program(cs, pack=pack).to_device(dev)
         say(f"[gpu] mixed {prefix} pack={pack}: {prog.depth} levels, widths {prog.level_widths()[:6]}...")
-        pool = _program_pool(prog, lk, bits, dev)
+        pool, _ = _program_pool(prog, ok, bits, dev)
         prog.run(lk, pool, form="int8")
         torch.cuda.synchronize()
         pools.append(to_host_u32(pool))
@@ -442,6 +442,38 @@ def test_packed_program_equals_earliest_level_schedule(toy, dev, prefix):
     for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(pools[1][np.array(c.outputs["out"]) + off]))
         assert got == OC.word_result(k, w, a, b), (k, w, a, b, got)
+
+
+def test_mixed_stream_std_oracle_replay(std, dev):
+    """A seeded mixed stream of 48 instructions (ADD/SUB, array MUL, LT/EQ,
+    bitwise; widths 8/16/32) at standard parameters, merged level by level
+    with the levels refilled to whole launch rounds (int8 form): every
+    instruction decrypts to its integer result, and one instance of each
+    kind (the narrowest available) replayed on the oracle from the same
+    encrypted inputs equals the GPU's pool word for word."""
+    from paper_2101_03403_amd import circuits as Cc
+    lk, ok = std
+    mix = W.instruction_mix(48, seed=29)
+    cs = [Cc.instruction_circuit(k, w) for k, w, _, _ in mix]
+    bits = []
+    for k, w, a, b in mix:
+        bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
+    prog = Cc.Program(cs, pack=256).to_device(dev)
+    say(f"[gpu] mixed std: {prog.num_gates()} gates in {prog.depth} levels")
+    pool, host0 = _program_pool(prog, ok, bits, dev, seed=91)
+    prog.run(lk, pool, form="int8")
+    torch.cuda.synchronize()
+    host = to_host_u32(pool)
+    for (k, w, a, b), c, off in zip(mix, cs, prog.offsets):
+        got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
+        assert got == OC.word_result(k, w, a, b), (k, w, a, b, got)
+    pick = {}
+    for i, (k, w, _, _) in enumerate(mix):
+        group = "BIT" if k in ("AND", "OR", "XOR") else k
+        if group not in pick or w < mix[pick[group]][1]:
+            pick[group] = i
+    say(f"[gpu] mixed std: replaying {sorted((mix[i][0], mix[i][1]) for i in pick.values())}")
+    _check_against_oracle_replay(ok, prog, host0, host, sorted(pick.values()), "mixed-stream replay")
 
 
 def test_tuning_variants_give_identical_results(std, dev):
@@ -453,8 +485,8 @@ def test_tuning_variants_give_identical_results(std, dev):
     lk, ok = std
     B = 45
     ops, a, b = W.gate_batch(B, seed=91)
-    c1 = lk.encrypt(a, seed=92)
-    c2 = lk.encrypt(b, seed=92, first_index=B)
+    c1 = O.encrypt_bits(ok, a, seed=92)
+    c2 = O.encrypt_bits(ok, b, seed=92, first_index=B)
     ref = None
     saved = cemu.get_tuning(lk)
     try:
@@ -484,7 +516,7 @@ def test_tuning_variants_give_identical_results(std, dev):
 
 def test_autotuner_picks_and_caches(std, dev, tmp_path):
     from paper_2101_03403_amd.autotune import CANDIDATES, Autotuner, bucket
-    lk, _ = std
+    lk, ok = std
     path = str(tmp_path / "tune.json")
     t = Autotuner(lk, cache_path=path, reps=1)
     form, tun = t.best(100)
@@ -500,11 +532,11 @@ def test_autotuner_picks_and_caches(std, dev, tmp_path):
 
 
 # ------------------------------------------------------------------ multiplexer and shifters
-def _mux_inputs(lk, B, seed):
+def _mux_inputs(ok, B, seed):
     rng = np.random.default_rng(seed)
     bits = rng.integers(0, 2, (3, B)).astype(np.uint8)
     bits[:, :8] = np.array([[0, 0, 0, 0, 1, 1, 1, 1], [0, 0, 1, 1, 0, 0, 1, 1], [0, 1, 0, 1, 0, 1, 0, 1]])
-    cts = [lk.encrypt(bits[r], seed=seed + r) for r in range(3)]
+    cts = [O.encrypt_bits(ok, bits[r], seed=seed + r) for r in range(3)]
     return bits, cts
 
 
@@ -529,7 +561,7 @@ def test_mux_toy_bit_exact(toy, dev):
     lk, ok = toy
     B = 37
     say(f"[gpu] mux toy B={B}")
-    bits, cts = _mux_inputs(lk, B, 71)
+    bits, cts = _mux_inputs(ok, B, 71)
     perm = np.random.default_rng(3).permutation(B + 5)[:B]
     got = _run_mux(lk, cts, dev, "int8", io_perm=perm)
     want = O.mux_batch(ok, *cts)
@@ -539,26 +571,24 @@ def test_mux_toy_bit_exact(toy, dev):
 
 @pytest.mark.parametrize("form", ["int8", "fft64"])
 def test_mux_std(std, dev, form):
-    """Standard parameters: decryptions exact; int8 bit-exact against the
-    oracle on sampled MUXes; FFT64 within the form's error bound."""
+    """Standard parameters: decryptions exact; sampled MUXes equal the
+    oracle's word for word in both forms (the FFT64 products round to the
+    exact integers)."""
     lk, ok = std
     B = 45
     say(f"[gpu] mux std {form} B={B}")
-    bits, cts = _mux_inputs(lk, B, 81)
+    bits, cts = _mux_inputs(ok, B, 81)
     got = _run_mux(lk, cts, dev, form)
     assert np.array_equal(lk.decrypt(got), np.where(bits[0] == 1, bits[1], bits[2]))
     idx = W.sample_indices(B, 6, seed=5)
     want = O.mux_batch(ok, cts[0][idx], cts[1][idx], cts[2][idx])
-    if form == "int8":
-        assert np.array_equal(got[idx], want)
-    else:
-        perr = to_i32(lk.phase(got[idx]).astype(np.int64) - lk.phase(want).astype(np.int64))
-        say(f"[gpu] mux fft64 vs oracle: max |phase error| = {np.abs(perr).max()}")
-        assert np.abs(perr).max() < (1 << 20)
+    diff = int(np.sum(got[idx] != want))
+    say(f"[gpu] mux {form} vs oracle: differing words {diff}/{want.size}")
+    assert diff == 0
 
 
 def test_mux_empty_and_errors(toy, dev):
-    lk, _ = toy
+    lk, ok = toy
     z = torch.zeros(0, dtype=torch.int32, device=dev)
     pool = torch.zeros((1, lk.n + 1), dtype=torch.int32, device=dev)
     cemu.mux(lk, pool, z, z, z, pool)           # B = 0 is a no-op
@@ -574,10 +604,11 @@ def test_mux_empty_and_errors(toy, dev):
 
 def test_program_shifters_levels_and_graph(std, dev):
     """32-bit LLS / LRS / ARS register-mode shifters (Sec. 5.4), 4 instances
-    each, merged level by level (5 levels of MUX batches): decryptions equal
-    the cleartext shifts; at every level 3 sampled MUXes are bit-exact against
-    the oracle on the GPU's own level inputs (int8 form); a captured hipGraph
-    replays the run exactly."""
+    each, merged level by level (5 levels of MUX batches, int8 form):
+    decryptions equal the cleartext shifts; one instance of each replayed on
+    the oracle from the same encrypted inputs (96 MUXes of every level)
+    equals the GPU's pool word for word; a captured hipGraph replays the run
+    exactly."""
     from paper_2101_03403_amd import circuits as Cc
     lk, ok = std
     rng = np.random.default_rng(55)
@@ -591,19 +622,14 @@ def test_program_shifters_levels_and_graph(std, dev):
     for k, w, a, b in cases:
         bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
     say(f"[gpu] shifters: {prog.num_muxes()} MUXes in {prog.depth} levels")
-    pool = _program_pool(prog, lk, bits, dev)
+    pool, host0 = _program_pool(prog, ok, bits, dev)
     prog.run(lk, pool, form="int8")
     torch.cuda.synchronize()
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
         assert got == OC.word_result(k, w, a, b), (k, a, b, got)
-    rs = np.random.default_rng(6)
-    for L in prog.levels:
-        ms, ma, mb, mo = L.mux
-        pick = rs.choice(ms.shape[0], 3, replace=False)
-        want = O.mux_batch(ok, host[ms[pick]], host[ma[pick]], host[mb[pick]])
-        assert np.array_equal(host[mo[pick]], want)
+    _check_against_oracle_replay(ok, prog, host0, host, [0, 4, 8], "shifter replay", min_per_level=64)
     eager = host.copy()
     g = prog.capture(lk, pool, form="int8")
     keep = torch.zeros(prog.rows, dtype=torch.bool, device=dev)
@@ -616,12 +642,14 @@ def test_program_shifters_levels_and_graph(std, dev):
         assert np.array_equal(to_host_u32(pool), eager), f"graph replay {rep} differs"
 
 
+@pytest.mark.timeout(600)
 def test_program_sequential_multiplier_and_divider(std, dev):
     """The paper's sequential multiplier (unsigned and signed) and the
     non-restoring divider (Sec. 5.5, 5.6), 8-bit, three instances each,
     merged level by level (FFT64 form, latency kernel): decryptions equal the
-    cleartext results; on every 8th level 2 sampled gates are bit-exact
-    against the oracle on the GPU's own level inputs."""
+    cleartext results; one signed multiplication and one division replayed
+    on the oracle from the same encrypted inputs (every gate of theirs, all
+    88 levels) equal the GPU's pool word for word."""
     from paper_2101_03403_amd import circuits as Cc
     lk, ok = std
     rng = np.random.default_rng(77)
@@ -633,7 +661,7 @@ def test_program_sequential_multiplier_and_divider(std, dev):
     for k, w, a, b in cases:
         bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
     say(f"[gpu] sequential units: {prog.num_gates()} gates in {prog.depth} levels")
-    pool = _program_pool(prog, lk, bits, dev)
+    pool, host0 = _program_pool(prog, ok, bits, dev)
     saved = cemu.get_tuning(lk)
     try:
         cemu.set_tuning(lk, fft_gates_per_wg=1)
@@ -645,15 +673,7 @@ def test_program_sequential_multiplier_and_divider(std, dev):
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
         assert got == OC.word_result(k, w, a, b), (k, a, b, got)
-    rs = np.random.default_rng(8)
-    for L in prog.levels[::8]:
-        if L.ops.shape[0] == 0:
-            continue
-        pick = rs.choice(L.ops.shape[0], min(2, L.ops.shape[0]), replace=False)
-        _, oout = O.bootstrap_batch(ok, L.ops[pick].astype(np.int32), host[L.ia[pick]], host[L.ib[pick]],
-                                    want_extracted=False)
-        assert np.array_equal(host[L.io[pick]], oout)
-
+    _check_against_oracle_replay(ok, prog, host0, host, [3, 6], "sequential units replay")
 
 
 def _t(a, dev):
@@ -673,7 +693,7 @@ def test_bootstrap_level_matches_separate_calls(std, dev, form):
     R, G, M = 40, 29, 13
     say(f"[gpu] bootstrap_level {form} G={G} M={M}")
     bits = rng.integers(0, 2, R).astype(np.uint8)
-    host_in = lk.encrypt(bits, seed=W.ENC_SEED + 40)
+    host_in = O.encrypt_bits(ok, bits, seed=W.ENC_SEED + 40)
     pool = to_dev(host_in, dev)
     ops_h = rng.integers(0, 10, G).astype(np.uint8)
     ia_h, ib_h = (rng.integers(0, R, G).astype(np.int32) for _ in range(2))
@@ -722,9 +742,9 @@ def test_bootstrap_level_matches_separate_calls(std, dev, form):
 def test_program_mux_prefix_levels_and_graph(std, dev):
     """ADD32, SUB32 and LT32 with the MUX prefix form (7 levels, gates and
     MUXes sharing launches), merged across instances, int8 form: decryptions
-    equal uint32 arithmetic; on every level 2 sampled gates and 2 sampled
-    MUXes are bit-exact against the oracle on the GPU's own level inputs; a
-    captured hipGraph replays the run exactly."""
+    equal uint32 arithmetic; one instance of each replayed on the oracle from
+    the same encrypted inputs equals the GPU's pool word for word; a captured
+    hipGraph replays the run exactly."""
     from paper_2101_03403_amd import circuits as Cc
     lk, ok = std
     rng = np.random.default_rng(321)
@@ -737,24 +757,14 @@ def test_program_mux_prefix_levels_and_graph(std, dev):
     for k, w, a, b in cases:
         bits += Cc.int_to_bits(a, w) + Cc.int_to_bits(b, w)
     say(f"[gpu] mux-prefix program: {prog.num_bootstraps()} blind rotations in {prog.depth} levels")
-    pool = _program_pool(prog, lk, bits, dev)
+    pool, host0 = _program_pool(prog, ok, bits, dev)
     prog.run(lk, pool, form="int8")
     torch.cuda.synchronize()
     host = to_host_u32(pool)
     for (k, w, a, b), c, off in zip(cases, cs, prog.offsets):
         got = Cc.bits_to_int(lk.decrypt(host[np.array(c.outputs["out"]) + off]))
         assert got == OC.word_result(k, w, a, b), (k, a, b, got)
-    rs = np.random.default_rng(9)
-    for L in prog.levels:
-        if L.ops.shape[0]:
-            pick = rs.choice(L.ops.shape[0], 2, replace=False)
-            _, oout = O.bootstrap_batch(ok, L.ops[pick].astype(np.int32), host[L.ia[pick]], host[L.ib[pick]],
-                                        want_extracted=False)
-            assert np.array_equal(host[L.io[pick]], oout)
-        if L.num_muxes:
-            ms, ma, mb, mo = L.mux
-            pick = rs.choice(ms.shape[0], 2, replace=False)
-            assert np.array_equal(host[mo[pick]], O.mux_batch(ok, host[ms[pick]], host[ma[pick]], host[mb[pick]]))
+    _check_against_oracle_replay(ok, prog, host0, host, [0, 5, 10], "mux-prefix replay")
     eager = host.copy()
     g = prog.capture(lk, pool, form="int8")
     keep = torch.zeros(prog.rows, dtype=torch.bool, device=dev)
@@ -776,7 +786,7 @@ def test_bootstrap_level_toy_bit_exact(toy, dev):
     R, G, M = 12, 9, 7
     say(f"[gpu] bootstrap_level toy G={G} M={M}")
     bits = rng.integers(0, 2, R).astype(np.uint8)
-    host_in = lk.encrypt(bits, seed=W.ENC_SEED + 41)
+    host_in = O.encrypt_bits(ok, bits, seed=W.ENC_SEED + 41)
     pool = to_dev(host_in, dev)
     ops_h = rng.integers(0, 10, G).astype(np.uint8)
     ia_h, ib_h = (rng.integers(0, R, G).astype(np.int32) for _ in range(2))
@@ -811,7 +821,7 @@ def test_batches_beyond_one_grid_pass(std, dev):
     work split in two calls that each fit one pass, and every decryption is
     exact. Batches beyond one blind-rotation launch are refused with a range
     error before anything is allocated or launched."""
-    lk, _ = std
+    lk, ok = std
     row = lk.n + 1
     one_pass = 1 << 24
 
@@ -846,8 +856,8 @@ def test_batches_beyond_one_grid_pass(std, dev):
     assert B * row > one_pass and (B // 2) * row <= one_pass
     say(f"[gpu] grid stride: {B} gates, fft64, one call against two")
     ops, a, b = W.gate_batch(B, seed=77)
-    c1 = lk.encrypt(a, seed=78)
-    c2 = lk.encrypt(b, seed=78, first_index=B)
+    c1 = O.encrypt_bits(ok, a, seed=78)
+    c2 = O.encrypt_bits(ok, b, seed=78, first_index=B)
     pool = to_dev(np.concatenate([c1, c2]), dev)
     ops_t = torch.from_numpy(np.ascontiguousarray(ops.astype(np.uint8))).to(dev)
     ia = torch.arange(B, dtype=torch.int32, device=dev)
@@ -867,7 +877,7 @@ def test_batches_beyond_one_grid_pass(std, dev):
     M = 17000
     assert M * (lk.N + 1) > one_pass and 2 * (M // 2) * row <= one_pass
     say(f"[gpu] grid stride: {M} MUXes, fft64, one call against two")
-    mbits, cts = _mux_inputs(lk, M, 93)
+    mbits, cts = _mux_inputs(ok, M, 93)
     mpool = to_dev(np.concatenate(cts), dev)
     rows = torch.arange(M, dtype=torch.int32, device=dev)
     mbig = torch.zeros((M, row), dtype=torch.int32, device=dev)
@@ -903,15 +913,15 @@ def test_int8_round_tail_split(std, dev):
     the device's CU count (a small and a long tail, and one just past the
     limit) equal, word for word, the one-gate kernel's output for the whole
     batch; every decryption is exact."""
-    lk, _ = std
+    lk, ok = std
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     saved = cemu.get_tuning(lk)
     try:
         for B in (16 * cus + 37, 16 * cus + 6 * cus, 16 * cus + 6 * cus + 1):
             say(f"[gpu] int8 tail split: B={B} (CUs {cus})")
             ops, a, b = W.gate_batch(B, seed=400 + B)
-            c1 = lk.encrypt(a, seed=401)
-            c2 = lk.encrypt(b, seed=401, first_index=B)
+            c1 = O.encrypt_bits(ok, a, seed=401)
+            c2 = O.encrypt_bits(ok, b, seed=401, first_index=B)
             cemu.set_tuning(lk, int8_waves=8, int8_gates_per_wg=16)
             _, got = run_gates(lk, ops, c1, c2, dev, form="int8", want_ext=False)
             cemu.set_tuning(lk, int8_waves=8, int8_gates_per_wg=1)
@@ -929,7 +939,7 @@ def test_fft_round_tail_split(std, dev):
     sized from the device's CU count take each path; every output equals,
     word for word, the latency kernel's output for the whole batch, and every
     decryption is exact."""
-    lk, _ = std
+    lk, ok = std
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     saved = cemu.get_tuning(lk)
     try:
@@ -937,8 +947,8 @@ def test_fft_round_tail_split(std, dev):
                       (8, 16 * cus + 5)):
             say(f"[gpu] fft tail split: fg={fg} B={B} (CUs {cus})")
             ops, a, b = W.gate_batch(B, seed=300 + B)
-            c1 = lk.encrypt(a, seed=301)
-            c2 = lk.encrypt(b, seed=301, first_index=B)
+            c1 = O.encrypt_bits(ok, a, seed=301)
+            c2 = O.encrypt_bits(ok, b, seed=301, first_index=B)
             cemu.set_tuning(lk, fft_gates_per_wg=fg)
             _, got = run_gates(lk, ops, c1, c2, dev, form="fft64", want_ext=False)
             cemu.set_tuning(lk, fft_gates_per_wg=1)

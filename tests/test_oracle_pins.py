@@ -158,6 +158,25 @@ def test_decomposition_range_and_precision(l, bgbit):
         assert np.all(rec % (1 << (32 - total)) == 0)
 
 
+# ------------------------------------------------------------------ exhaustive over all 2^32 words
+@pytest.mark.slow
+def test_modswitch_and_decomposition_exhaustive(tmp_path):
+    """Every uint32 word: the modulus switch (2N = 1024 and 2048) is the
+    nearest integer of x * 2N / 2^32 modulo 2N with ties up, and the l = 3,
+    Bgbit = 7 decomposition has digits in [-64, 64) recomposing to the nearest
+    multiple of 2^11 (ties up). The checks are a small C program
+    (tests/exhaustive_pins.c) linked with the oracle's source."""
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "exhaustive_pins")
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", os.path.join(here, "exhaustive_pins.c"),
+                           os.path.join(os.path.dirname(here), "oracle", "oracle.c"), "-lm", "-o", exe])
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=600)
+    print(r.stdout)
+    counts = [int(line.split()[-1]) for line in r.stdout.strip().splitlines()]
+    assert len(counts) == 5 and sum(counts) == 0 and r.returncode == 0
+
+
 def test_decomposition_of_zero_is_zero():
     assert np.all(O.decompose(0, 3, 7) == 0)
 
