@@ -185,6 +185,26 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ck, int form, const uint8_t *ops,
                          const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out,
                          int64_t B, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * gates as cemu_bootstrap_gates, same arguments and the same outputs bit for
+ * bit, with no hipMalloc, hipFree or other allocation in the call. The
+ * workspace is a fixed scratch array in the library's device code (22 MiB
+ * on each GPU the library runs on, held until the process ends; its address
+ * is looked up at key generation), so B is limited to
+ * CEMU_NOALLOC_MAX_GATES. Every call on one GPU shares that one array:
+ * calls whose work overlaps in time on the same GPU (several streams or host
+ * threads, any cloud keys) race and produce wrong ciphertexts, so serialise
+ * them, e.g. on one stream. Each call writes every scratch word it reads, so
+ * nothing carries over from the previous call. Kernel timing
+ * (cemu_profile_enable) records nothing for this entry point.
+ * Errors: as cemu_bootstrap_gates, plus CEMU_ERR_RANGE for
+ * B > CEMU_NOALLOC_MAX_GATES. */
+#define CEMU_NOALLOC_MAX_GATES 4096
+int cemu_bootstrap_gates_noalloc(const cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool_in,
+                                 const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out,
+                                 int64_t B, void *hip_stream);
+
 /* The same gates without the final key switch (steps 1-4 above): writes
  * the extracted dimension-N samples, which encrypt +-1/8 under the TRLWE
  * key's coefficients. This is the half of a gate that TFHE's MUX runs twice

@@ -53,7 +53,7 @@ class Params(C.Structure):
 
 EXPORTED = [
     "cemu_params_default", "cemu_keygen", "cemu_secret_params", "cemu_cloud_params", "cemu_encrypt",
-    "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates",
+    "cemu_decrypt", "cemu_decrypt_extracted", "cemu_phase", "cemu_bootstrap_gates", "cemu_bootstrap_gates_noalloc",
     "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_mux", "cemu_bootstrap_level", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
     "cemu_profile_enable", "cemu_profile_read", "cemu_get_tuning", "cemu_set_tuning",
@@ -82,6 +82,7 @@ def lib() -> C.CDLL:
     L.cemu_decrypt_extracted.argtypes = [vp, vp, i64, vp]
     L.cemu_phase.argtypes = [vp, C.c_int, vp, i64, vp]
     L.cemu_bootstrap_gates.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.cemu_bootstrap_gates_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_blind_rotate_extract.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_key_switch.argtypes = [vp, vp, vp, i64, vp]
     L.cemu_mux.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
@@ -283,6 +284,20 @@ def bootstrap_gates(keys: Keys, ops, pool_in, ia, ib, pool_out, io=None, form="i
                                       _dptr(pool_out, "pool_out", "words", width=keys.n + 1,
                                             min_rows=B if io is None else None),
                                       B, _stream(stream)))
+
+
+def bootstrap_gates_noalloc(keys: Keys, ops, pool_in, ia, ib, pool_out, io=None, form="int8", stream=None):
+    """The allocation-free variant (at most NOALLOC_MAX_GATES gates; calls on
+    one GPU must not overlap); see cemu_bootstrap_gates_noalloc."""
+    B = int(ops.shape[0])
+    _check(lib().cemu_bootstrap_gates_noalloc(keys.ck, FORMS[form], *_gate_args(keys, ops, pool_in, ia, ib, B),
+                                              _dptr(io, "io", "rows", rows=B),
+                                              _dptr(pool_out, "pool_out", "words", width=keys.n + 1,
+                                                    min_rows=B if io is None else None),
+                                              B, _stream(stream)))
+
+
+NOALLOC_MAX_GATES = 4096
 
 
 def blind_rotate_extract(keys: Keys, ops, pool_in, ia, ib, out_N, form="int8", stream=None):

@@ -625,19 +625,25 @@ int br_fft_batch_ok(const cemu_cloud_key *ck, int64_t B)
     return CEMU_OK;
 }
 
+int build_bk_fft(cemu_cloud_key *ck, hipStream_t s)
+{
+    if (ck->p.N != FN) return fail(CEMU_ERR_UNSUPPORTED, "the FFT64 form is built for N = 1024");
+    if (ck->d_bkfft) return CEMU_OK;
+    const size_t polys = (size_t)ck->p.n * 6 * 2;
+    if (hipMalloc(&ck->d_bkfft, polys * FH * sizeof(d2)) != hipSuccess)
+        return fail(CEMU_ERR_OOM, "device allocation (FFT key) failed");
+    hipLaunchKernelGGL(bk_fft_prepare_kernel, dim3((unsigned)polys), dim3(64), 0, s, ck->d_bk8,
+                       reinterpret_cast<d2 *>(ck->d_bkfft));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("bk_fft_prepare launch: ") + hipGetErrorString(e));
+    return CEMU_OK;
+}
+
 int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s)
 {
     if (ck->p.N != FN) return fail(CEMU_ERR_UNSUPPORTED, "the FFT64 form is built for N = 1024");
     const int n = ck->p.n;
-    if (!ck->d_bkfft) {
-        const size_t polys = (size_t)n * 6 * 2;
-        if (hipMalloc(&ck->d_bkfft, polys * FH * sizeof(d2)) != hipSuccess)
-            return fail(CEMU_ERR_OOM, "device allocation (FFT key) failed");
-        hipLaunchKernelGGL(bk_fft_prepare_kernel, dim3((unsigned)polys), dim3(64), 0, s, ck->d_bk8,
-                           reinterpret_cast<d2 *>(ck->d_bkfft));
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return fail(CEMU_ERR_HIP, std::string("bk_fft_prepare launch: ") + hipGetErrorString(e));
-    }
+    if (const int rc = build_bk_fft(ck, s)) return rc;   // normally done at key generation
     if (const int rc = br_fft_batch_ok(ck, B)) return rc;
     const int fg = ck->tuning.fft_gates_per_wg;
     const d2 *spec = reinterpret_cast<const d2 *>(ck->d_bkfft);

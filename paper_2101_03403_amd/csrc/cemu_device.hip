@@ -243,6 +243,38 @@ bool ks_valu_forced()
 }
 
 
+// Fixed scratch of cemu_bootstrap_gates_noalloc, for callers that cannot
+// allocate: the rescaled masks (u16 [B][n+1], n + 1 <= 768) and then the
+// extracted samples (u32 [B][N+1], N <= 1024) of up to CEMU_NOALLOC_MAX_GATES
+// gates, 22 MiB, present on every device the library runs on until the
+// process ends. Host code must never pass the array's name to a kernel: on
+// the host it is a stand-in, not a device address. The address of each
+// device's copy comes from hipGetSymbolAddress with that device current.
+constexpr size_t kNoallocBarsBytes = (size_t)CEMU_NOALLOC_MAX_GATES * (CEMU_MAX_KEY_N + 1) * sizeof(uint16_t);
+constexpr size_t kNoallocExtBytes = (size_t)CEMU_NOALLOC_MAX_GATES * (1024 + 1) * sizeof(uint32_t);
+static_assert(kNoallocBarsBytes % 256 == 0, "the sample region starts 256-byte aligned");
+__device__ __align__(256) uint8_t scratch[kNoallocBarsBytes + kNoallocExtBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current: looked
+// up once per device (at key generation) and cached.
+int noalloc_scratch(int dev, uint8_t **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(CEMU_ERR_PARAM, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(CEMU_ERR_HIP, hip_msg("hipGetSymbolAddress (scratch)", e));
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return CEMU_OK;
+}
+
 int ensure_workspace(cemu_cloud_key *ck, int64_t B, bool need_ext)
 {
     const int32_t n = ck->p.n, N = ck->p.N;
@@ -323,26 +355,27 @@ int check_device(const cemu_cloud_key *ck)
     return CEMU_OK;
 }
 
-// Blind rotation + extraction of the B gates whose bars are in the workspace.
-int run_br(cemu_cloud_key *ck, int form, uint32_t *ext_out, int64_t B, hipStream_t s)
+// Blind rotation + extraction of the B gates whose rescaled masks are in bars.
+int run_br(cemu_cloud_key *ck, int form, const uint16_t *bars, uint32_t *ext_out, int64_t B, hipStream_t s)
 {
     int rc;
     void *ev = prof_begin(ck, s);
-    if (form == CEMU_FORM_INT8) rc = launch_br_int8(ck, ck->d_bars, B, ext_out, s);
-    else if (form == CEMU_FORM_FFT64) rc = launch_br_fft(ck, ck->d_bars, B, ext_out, s);
+    if (form == CEMU_FORM_INT8) rc = launch_br_int8(ck, bars, B, ext_out, s);
+    else if (form == CEMU_FORM_FFT64) rc = launch_br_fft(ck, bars, B, ext_out, s);
     else rc = fail(CEMU_ERR_PARAM, "unknown product form");
     if (rc == CEMU_OK) prof_end(ck, form == CEMU_FORM_INT8 ? 1 : 2, s, ev);
     else if (ev) (void)hipEventDestroy((hipEvent_t)ev);
     return rc;
 }
 
-// Lincomb + blind rotation + extraction into ext_out ([B][N+1]).
+// Lincomb + blind rotation + extraction into ext_out ([B][N+1]); bars is
+// the [B][n+1] workspace of the rescaled masks.
 int run_blind_rotate(cemu_cloud_key *ck, int form, const uint8_t *ops, const uint32_t *pool, const int32_t *ia,
-                     const int32_t *ib, uint32_t *ext_out, int64_t B, hipStream_t s)
+                     const int32_t *ib, uint16_t *bars, uint32_t *ext_out, int64_t B, hipStream_t s)
 {
-    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, ck->d_bars, s);
+    int rc = launch_lincomb(ck, ops, pool, ia, ib, B, bars, s);
     if (rc) return rc;
-    return run_br(ck, form, ext_out, B, s);
+    return run_br(ck, form, bars, ext_out, B, s);
 }
 
 // G gates and M multiplexers through one blind-rotation launch and one key
@@ -363,7 +396,7 @@ int run_level(cemu_cloud_key *ck, int form, const uint32_t *pool, const uint8_t 
         CEMU_HIP(hipGetLastError());
         prof_end(ck, 0, s, ev);
     }
-    rc = run_br(ck, form, ck->d_ext, G + 2 * M, s);
+    rc = run_br(ck, form, ck->d_bars, ck->d_ext, G + 2 * M, s);
     if (rc) return rc;
     if (M > 0) {
         hipLaunchKernelGGL(mux_combine_kernel, elem_grid(M * (N + 1)), dim3(kElemThreads), 0, s,
@@ -422,7 +455,20 @@ int upload_cloud_key(cemu_cloud_key *ck, const std::vector<uint8_t> &bk8, const 
         release_cloud_key(ck);
         return fail(CEMU_ERR_HIP, hip_msg("hipMemcpy (key upload)", e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3)));
     }
-    return CEMU_OK;
+    // the FFT form of the key, and this device's address of the fixed
+    // scratch, so that later gate calls need no set-up
+    int rc = CEMU_OK;
+    if (ck->p.N == 1024) {
+        rc = build_bk_fft(ck, nullptr);
+        if (rc == CEMU_OK) {
+            const hipError_t e = hipStreamSynchronize(nullptr);
+            if (e != hipSuccess) rc = fail(CEMU_ERR_HIP, hip_msg("FFT key preparation", e));
+        }
+    }
+    uint8_t *scr = nullptr;
+    if (rc == CEMU_OK) rc = noalloc_scratch(ck->device, &scr);
+    if (rc != CEMU_OK) release_cloud_key(ck);
+    return rc;
 }
 
 int download_bk8(const cemu_cloud_key *ck, std::vector<uint8_t> &bk8)
@@ -485,9 +531,47 @@ int cemu_bootstrap_gates(const cemu_cloud_key *ckc, int form, const uint8_t *ops
     rc = ensure_workspace(ck, B, true);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)hip_stream;
-    rc = run_blind_rotate(ck, form, ops, pool_in, ia, ib, ck->d_ext, B, s);
+    rc = run_blind_rotate(ck, form, ops, pool_in, ia, ib, ck->d_bars, ck->d_ext, B, s);
     if (rc) return rc;
     return launch_key_switch(ck, ck->d_ext, io, pool_out, B, s);
+}
+
+int cemu_bootstrap_gates_noalloc(const cemu_cloud_key *ckc, int form, const uint8_t *ops, const uint32_t *pool_in,
+                                 const int32_t *ia, const int32_t *ib, const int32_t *io, uint32_t *pool_out,
+                                 int64_t B, void *hip_stream)
+{
+    clear_error();
+    if (!ckc) return fail(CEMU_ERR_NULL, "cloud key is NULL");
+    if (B < 0) return fail(CEMU_ERR_RANGE, "B < 0");
+    if (form != CEMU_FORM_INT8 && form != CEMU_FORM_FFT64) return fail(CEMU_ERR_PARAM, "unknown product form");
+    if (B == 0) return CEMU_OK;
+    if (B > CEMU_NOALLOC_MAX_GATES)
+        return fail(CEMU_ERR_RANGE, "batch larger than the fixed scratch of cemu_bootstrap_gates_noalloc "
+                                    "(CEMU_NOALLOC_MAX_GATES = 4096 gates)");
+    if (!ops || !pool_in || !ia || !ib || !pool_out) return fail(CEMU_ERR_NULL, "NULL device buffer");
+    if (misaligned(pool_in) || misaligned(ia) || misaligned(ib) || misaligned(pool_out) || (io && misaligned(io)))
+        return fail(CEMU_ERR_ALIGN, "device buffers must be 4-byte aligned");
+    cemu_cloud_key *ck = const_cast<cemu_cloud_key *>(ckc);
+    std::lock_guard<std::mutex> lock(ck->mu);
+    int rc = check_device(ck);
+    if (rc) return rc;
+    if ((rc = check_br_batch(ck, form, B))) return rc;
+    if (form == CEMU_FORM_FFT64 && !ck->d_bkfft)
+        return fail(CEMU_ERR_UNSUPPORTED, "the FFT64 form needs N = 1024 (its key is built at key generation)");
+    uint8_t *scr = nullptr;
+    if ((rc = noalloc_scratch(ck->device, &scr))) return rc;
+    // the masks, then the extracted samples: every word of both is written
+    // before it is read, so nothing needs clearing between calls
+    uint16_t *bars = reinterpret_cast<uint16_t *>(scr);
+    uint32_t *ext = reinterpret_cast<uint32_t *>(scr + kNoallocBarsBytes);
+    // kernel timing creates events; this entry point records none
+    const bool profiling = ck->profiling;
+    ck->profiling = false;
+    hipStream_t s = (hipStream_t)hip_stream;
+    rc = run_blind_rotate(ck, form, ops, pool_in, ia, ib, bars, ext, B, s);
+    if (rc == CEMU_OK) rc = launch_key_switch(ck, ext, io, pool_out, B, s);
+    ck->profiling = profiling;
+    return rc;
 }
 
 int cemu_mux(const cemu_cloud_key *ckc, int form, const uint32_t *pool_in, const int32_t *is, const int32_t *ia,
@@ -558,7 +642,7 @@ int cemu_blind_rotate_extract(const cemu_cloud_key *ckc, int form, const uint8_t
     if ((rc = check_br_batch(ck, form, B))) return rc;
     rc = ensure_workspace(ck, B, false);
     if (rc) return rc;
-    return run_blind_rotate(ck, form, ops, pool_in, ia, ib, out_N, B, (hipStream_t)hip_stream);
+    return run_blind_rotate(ck, form, ops, pool_in, ia, ib, ck->d_bars, out_N, B, (hipStream_t)hip_stream);
 }
 
 int cemu_key_switch(const cemu_cloud_key *ck, const uint32_t *in_N, uint32_t *out_n, int64_t B, void *hip_stream)

@@ -13,6 +13,10 @@ namespace cemu {
 int launch_br_int8(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
 int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t *ext, hipStream_t s);
 
+// The FFT form of the bootstrapping key (ck->d_bkfft), allocated and computed
+// on stream s if it is not there yet; N = 1024 only.
+int build_bk_fft(cemu_cloud_key *ck, hipStream_t s);
+
 // CEMU_OK if one launch of the key's current shape for the form holds B
 // blind rotations (a dispatch counts at most 2^32 - 1 work-items), else
 // CEMU_ERR_RANGE with the message set. The launchers check it too.
