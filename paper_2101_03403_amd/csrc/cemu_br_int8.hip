@@ -279,25 +279,37 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
 // negated half is exact). X is stored four times, copy r shifted down by r
 // bytes, so a lane whose 16-byte window starts at byte s reads four whole
 // dwords from copy s & 3 and forms its fragment without byte alignment
-// instructions. The B operand holds the key: column
-// n = 4 q + kappa (n < 8) is limb kappa of BK_i[p][q], columns 8..15 are
-// zero. One 16x16x64 MFMA thus produces every limb of both outputs; the
-// limbs are recombined across the four lanes of a quad (shift by 8 kappa,
-// then a reduce-scatter with two DPP exchanges that leaves each lane one
-// full row) and each wave adds its share into ACC with LDS integer atomics,
-// which wrap modulo 2^32 like the sum itself, so the order of the adds does
-// not matter and the result is bit-exact. Inside a lane's 16-byte
-// group the k order is reversed in both operands (k = k0 + 16 g + 15 - t for
-// byte t), which turns the key's reversed storage (BK[m] at byte N - 1 - m)
-// into one aligned 16-byte load per K-tile and leaves X in natural order.
-// Waves: component c (its 3 digit rows), output half mh (N/2 rows), and for
-// WAVES = 8 a half ks of the K-tiles of each row.
+// instructions.
+//
+// One level of the negacyclic half split: with H = N/2, T_p is the block
+// matrix [[P, -Q], [Q, P]] of two H x H Toeplitz blocks, P[m][k] =
+// E_p[m - k] and Q[m][k] = E_p[m - k + H] (the upper-right block is -Q
+// because E_p[s - H] = -E_p[s + H] for the wrap). With the key split into
+// halves k0 (coefficients < H) and k1, the product is
+//   y0 = P k0 - Q k1,   y1 = Q k0 + P k1,
+// two block products of half size, each against both key halves. The B
+// operand holds the key limbs in all 16 columns: column n = 8 h + 4 q +
+// kappa is limb kappa of half h of BK_i[p][q]. So one MFMA over a block
+// serves both halves, and a digit row costs two H x H products (N^2 / 2
+// multiply-adds in 16-column MFMAs) instead of one N x N product in which
+// half of the columns would be zero.
+//
+// The limbs are recombined across the four lanes of a quad (shift by
+// 8 kappa, then a reduce-scatter with two DPP exchanges that leaves each
+// lane one full row) and each lane adds its row into ACC with an LDS integer
+// atomic, negated for the -Q k1 term; the adds wrap modulo 2^32 like the sum
+// itself, so their order does not matter and the result is bit-exact.
+// Inside a lane's 16-byte group the k order is reversed in both operands
+// (k = k0 + 16 g + 15 - t for byte t), which turns the key's reversed storage
+// (BK[m] at byte N - 1 - m) into one aligned 16-byte load per K-tile and
+// leaves X in natural order. Waves: component c (its 3 digit rows), block
+// pr (P or Q), and for WAVES = 8 a half ks of the K-tiles of each row.
 template <int N, int WAVES>
 struct LatShape {
     static constexpr int THREADS = 64 * WAVES;
-    static constexpr int KS = WAVES / 4;            // K-splits per (component, output half)
-    static constexpr int MT = N / 32;               // 16-row M-tiles per wave (N/2 rows)
-    static constexpr int KT = N / 64 / KS;          // 64-wide K-tiles per wave and digit row
+    static constexpr int KS = WAVES / 4;            // K-splits per (component, block)
+    static constexpr int MT = N / 32;               // 16-row M-tiles per wave (the N/2 rows of a block)
+    static constexpr int KT = N / 128 / KS;         // 64-wide K-tiles per wave and digit row (N/2 columns)
     static constexpr int NDELTA = MT + 4 * (KT - 1);
     static constexpr int XD = N / 2;                // dwords per extended digit row X_p
     static constexpr int XCOPY = BR_ROWS * XD + 8;  // dwords per shifted copy; +8 staggers the copies' banks
@@ -341,7 +353,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
     __shared__ __attribute__((aligned(16))) uint32_t xs[4 * S::XCOPY];   // copy r, row p, dword w
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ks = wave % S::KS, mh = (wave / S::KS) & 1, c = wave / (2 * S::KS);
+    const int ks = wave % S::KS, pr = (wave / S::KS) & 1, c = wave / (2 * S::KS);
     const int col = lane & 15, g4 = lane >> 4;
     const int64_t g = blockIdx.x;   // the grid has exactly one workgroup per gate
     const uint16_t *bar = bars + g * (int64_t)(n + 1);
@@ -354,22 +366,23 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
         acc_s[1][m] = tt < (uint32_t)N ? 0x20000000u : 0xE0000000u;
     }
 
-    // A fragment source of this lane: byte offset s0 in X_p (1 <= s0, and the
-    // last fragment ends at byte 2N - 1), read as dword s0 / 4 of copy s0 & 3.
-    const int s0 = N + 16 * S::MT * mh - 64 * S::KT * ks + col - 16 * g4 - 15 - 64 * (S::KT - 1);
+    // A fragment source of this lane: byte offset s0 in X_p, block Q starting
+    // N/2 bytes after block P (s0 >= 1, and the last fragment of Q ends at byte
+    // 2N - 1), read as dword s0 / 4 of copy s0 & 3.
+    const int s0 = N + (N / 2) * pr - 64 * S::KT * ks + col - 16 * g4 - 15 - 64 * (S::KT - 1);
     const uint32_t *xsrc = xs + (s0 & 3) * S::XCOPY + (s0 >> 2);
 
-    // B fragments: limb kappa of BK_i[p][q] for k in the lane's 16-byte group,
-    // read reversed from the key (byte N - 16 - k0 - 16 g4 .. + 15); columns
-    // 8..15 stay zero.
-    const bool bcol = col < 8;
-    const size_t bplane = bcol ? (size_t)col * (2 * N) : 0;   // plane (q, kappa) = (col >> 2, col & 3)
+    // B fragments: limb kappa of half h of BK_i[p][q] (column 8 h + 4 q +
+    // kappa) for k in the lane's 16-byte group, read reversed from the key
+    // (byte N - 16 - k0 - 16 g4 .. + 15 for half 0, N/2 bytes lower for half 1).
+    const int bhalf = col >> 3;
+    const size_t bplane = (size_t)(col & 7) * (2 * N);   // plane (q, kappa) = ((col & 7) >> 2, col & 3)
     auto load_b = [&](int step, int row, v4i (&dst)[S::KT]) {
         const uint8_t *src = bk8 + ((size_t)step * BR_ROWS + row) * (2 * 4 * 2 * N) + bplane;
         static_for<0, S::KT>([&](auto bI) {
             constexpr int b = decltype(bI)::value;
-            const int u0 = N - 16 - 64 * (S::KT * ks + b) - 16 * g4;
-            const u4 v = bcol ? *reinterpret_cast<const u4 *>(src + u0) : u4{0u, 0u, 0u, 0u};
+            const int u0 = N - 16 - 64 * (S::KT * ks + b) - 16 * g4 - (N / 2) * bhalf;
+            const u4 v = *reinterpret_cast<const u4 *>(src + u0);
             dst[b] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
         });
     };
@@ -442,16 +455,19 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
             load_b(ni, 3 * c + (j < 2 ? j + 1 : 0), nb);
             lat_mfma_block<N, WAVES>(xsrc + (3 * c + j) * S::XD, acc, bf);
         }
-        // Delta_q[m] = sum_kappa 2^(8 kappa) C[m][4 q + kappa]: the four limbs
-        // of an output row sit in the four lanes of a quad (lanes 4q .. 4q+3 of
-        // a 16-lane row), each lane holding rows 4 g4 + e, e = 0..3. A
-        // reduce-scatter over the quad (exchange with lane ^ 1, then lane ^ 2)
-        // leaves lane kappa with the full sum of row e = kappa, so one atomic
-        // add per lane and tile updates ACC_q (lanes 8..15 of a row hold the
-        // zero columns and stay out).
+        // The block product's column 8 h + 4 q + kappa holds limb kappa of
+        // (block x key half h) for output q: sum_kappa 2^(8 kappa) C[m][.].
+        // The four limbs of an output row sit in the four lanes of a quad,
+        // each lane holding rows 4 g4 + e, e = 0..3. A reduce-scatter over the
+        // quad (exchange with lane ^ 1, then lane ^ 2) leaves lane kappa with
+        // the full sum of row e = kappa. Block P times half h goes to output
+        // half h (+P k0 into y0, +P k1 into y1); block Q times half 0 goes to
+        // y1 (+Q k0) and times half 1 to y0 (-Q k1).
         const uint32_t lsh = 8u * (uint32_t)(lane & 3);
-        const bool odd = (lane & 1) != 0, hi2 = (lane & 2) != 0, writer = (lane & 8) == 0;
-        uint32_t *accq = acc_s[(lane >> 2) & 1] + 4 * g4 + (lane & 3);
+        const bool odd = (lane & 1) != 0, hi2 = (lane & 2) != 0;
+        const int out_half = pr ? 1 - bhalf : bhalf;
+        const bool negate = pr && bhalf;
+        uint32_t *accq = acc_s[(lane >> 2) & 1] + (N / 2) * out_half + 4 * g4 + (lane & 3);
         static_for<0, S::MT>([&](auto tI) {
             constexpr int t = decltype(tI)::value;
             const uint32_t v0 = (uint32_t)acc[t][0] << lsh, v1 = (uint32_t)acc[t][1] << lsh;
@@ -464,7 +480,7 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_lat_kernel(const uint8_
             const uint32_t z1 = (odd ? v3 : v2) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(odd ? v2 : v3), 0xB1, 0xF, 0xF, false);
             // keep row e = lane & 3, pass the other to lane ^ 2 (quad_perm [2,3,0,1])
             const uint32_t r = (hi2 ? z1 : z0) + (uint32_t)__builtin_amdgcn_mov_dpp((int)(hi2 ? z0 : z1), 0x4E, 0xF, 0xF, false);
-            if (writer) atomicAdd(accq + 16 * (S::MT * mh + t), r);
+            atomicAdd(accq + 16 * t, negate ? 0u - r : r);
         });
     }
     __syncthreads();
