@@ -33,12 +33,10 @@ N_, n_, ROWS = 1024, 630, 6
 INT8_OPS_PER_GATE = n_ * ROWS * 2 * N_ * N_ * 4 * 2
 PEAK_INT8_OPS = 5.0e15          # MI355X dense int8 MFMA, ops/s
 PEAK_FP64_FLOPS = 78.6e12        # MI355X FP64 vector, flop/s
-# The same peaks as measured on MI355X with independent-chain throughput
-# probes at the kernels' occupancy (two waves per SIMD, one workgroup per CU):
-# FP64 FMA 69.6 TFLOP/s, v_mfma_i32_16x16x64_i8 4.9e15 op/s (short bursts, at
-# full clock). Reported beside the spec peaks.
-MEASURED_FP64_FLOPS = 69.6e12
-MEASURED_INT8_OPS = 4.9e15
+# Beside these published peaks the benchmark reports fractions of the peaks
+# measured on the device it runs on (cemu_measure_peaks: independent FP64
+# FMA chains and independent int8 MFMA accumulations at the kernels'
+# occupancy, two waves per SIMD, one workgroup per compute unit).
 # FP64-FFT form per gate: n steps x (8 FFTs of 512 points at 5 n log2 n + twist
 # 6 x 512, plus 12 x 512 complex multiply-adds at 8 flop).
 FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
@@ -97,6 +95,9 @@ def parse():
     ap.add_argument("--only", action="store_true", help="time only --form")
     ap.add_argument("--fft-gates-per-wg", type=int, default=8, choices=[1, 4, 8],
                     help="FFT64 launch shape of the throughput loop (1 = the one-gate-per-workgroup latency kernel)")
+    ap.add_argument("--int8-gates-per-wg", type=int, default=16, choices=[1, 16],
+                    help="int8 launch shape of the throughput loop (1 = the one-gate-per-workgroup latency kernel)")
+    ap.add_argument("--int8-waves", type=int, default=8, choices=[4, 8])
     ap.add_argument("--batch", type=int, default=BATCH)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=512,
@@ -109,6 +110,8 @@ def parse():
     ap.add_argument("--add-instances", type=int, default=256)
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed instruction stream")
     ap.add_argument("--no-autotune", action="store_true", help="circuits use --form with default tiles")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure the FP64 FMA and int8 MFMA peak rates on this GPU, print them and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit; "
                          "used to scale HBM byte counters")
@@ -231,17 +234,21 @@ def run_form(keys, form, ops_t, pool, ia, ib, out, stream, steps, warmup):
     torch.cuda.synchronize()
     cemu.profile_read(keys)                       # drop anything recorded so far
     cemu.profile_enable(keys, True)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    events[0].record(stream)
+    for k in range(steps):
         step()
+        events[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cemu.profile_enable(keys, False)
-    return wall, cemu.profile_read(keys)
+    per_step = [events[k].elapsed_time(events[k + 1]) for k in range(steps)]
+    return wall, cemu.profile_read(keys), per_step
 
 
-def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="gates", kind="ADD"):
+def add32_latency(keys, dev, form, instances=256, reps=10, tuner=None, prefix="gates", kind="ADD"):
     """32-bit Kogge-Stone ADD (Sec. 5.2) or SUB (Sec. 5.3, kind="SUB"):
     `instances` concurrent instructions with all gates of a level in one
     launch, the levels (12 with the paper's AND/OR prefix, 7 with the MUX
@@ -293,7 +300,7 @@ def add32_latency(keys, dev, form, instances=256, reps=3, tuner=None, prefix="ga
     return out
 
 
-def shift32_latency(keys, dev, form, reps=3, tuner=None):
+def shift32_latency(keys, dev, form, reps=10, tuner=None):
     """32-bit register-mode barrel shifters LLS / LRS / ARS (Sec. 5.4): one
     instance each, 5 levels of 32 FHE MUX selects, captured as a hipGraph;
     latency = median replay. The paper reports 474.7 / 472.9 / 491.8 ms on
@@ -329,11 +336,11 @@ def shift32_latency(keys, dev, form, reps=3, tuner=None):
                      "bootstraps": prog.num_bootstraps(), "levels": prog.depth,
                      "decrypt_exact": int(got == expected_word(mode, 32, a, amt))}
     out["form"] = form if tuner is None else "autotuned per launch width"
-    out["timing"] = "hipGraph of the 5 MUX levels, median of 3 replays (hip events)"
+    out["timing"] = f"hipGraph of the 5 MUX levels, median of {reps} replays (hip events)"
     return out
 
 
-def sequential_units(keys, dev, form, width=32, reps=2, tuner=None, prefix="gates"):
+def sequential_units(keys, dev, form, width=32, reps=3, tuner=None, prefix="gates"):
     """The paper's sequential multiplier (unsigned and signed) and the
     non-restoring divider (Sec. 5.5, 5.6), one instance each: W iterations
     of a W- or (W+1)-bit adder, hundreds of narrow levels, captured as a
@@ -506,14 +513,18 @@ def noise_chain(keys, form, out1, want1, seed=3):
             "inputs": "the first level's outputs (key-switched, not fresh), two random permutations"}
 
 
-def roofline(form, prof, B, fft_gates_per_wg=8):
+def roofline(form, prof, B, peaks, fft_gates_per_wg=8, int8_gates_per_wg=16, int8_waves=8):
     if form == "int8":
+        kname = (f"br_int8_kernel<1024, {int8_waves}>" if int8_gates_per_wg == 16
+                 else f"br_int8_lat_kernel<1024, {int8_waves}>")
+        default_shape = int8_gates_per_wg == 16 and int8_waves == 8
         ms, cnt = prof["blind_rotate_int8"]
         avg = ms / max(cnt, 1)
         ach = INT8_OPS_PER_GATE * B / (avg * 1e-3)
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_INT8_OPS / 1e12, "unit": "TOP/s",
-                "frac": ach / PEAK_INT8_OPS, "traffic": traffic_bytes("int8", B), "kernel": "br_int8_kernel<1024, 8>",
-                "measured_peak": MEASURED_INT8_OPS / 1e12, "frac_measured": ach / MEASURED_INT8_OPS,
+                "frac": ach / PEAK_INT8_OPS, "traffic": traffic_bytes("int8", B) if default_shape else None,
+                "kernel": kname,
+                "measured_peak": peaks["int8_ops_per_s"] / 1e12, "frac_measured": ach / peaks["int8_ops_per_s"],
                 "avg_ms": avg, "algorithmic_per_launch": INT8_OPS_PER_GATE * B,
                 "algorithmic_per_gate": "n*2l*2*N^2*4 limbs*2 = 6.34e10 int8 ops"}
     ms, cnt = prof["blind_rotate_fft64"]
@@ -522,7 +533,7 @@ def roofline(form, prof, B, fft_gates_per_wg=8):
     return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
             "frac": ach / PEAK_FP64_FLOPS, "traffic": traffic_bytes("fft64", B) if fft_gates_per_wg == 8 else None,
             "kernel": FFT_KERNEL[fft_gates_per_wg],
-            "measured_peak": MEASURED_FP64_FLOPS / 1e12, "frac_measured": ach / MEASURED_FP64_FLOPS,
+            "measured_peak": peaks["fp64_flops_per_s"] / 1e12, "frac_measured": ach / peaks["fp64_flops_per_s"],
             "avg_ms": avg, "algorithmic_per_launch": FFT_FLOP_PER_GATE * B,
             "algorithmic_per_gate": "n*(8*(5*512*9 + 6*512) + 12*512*8) = 1.63e8 FP64 flop"}
 
@@ -569,8 +580,15 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
         return
+    peaks = cemu.measure_peaks()
+    peaks["how"] = ("cemu_measure_peaks on this GPU: independent FP64 FMA chains and int8 MFMA accumulations, "
+                    "one workgroup of 8 waves per compute unit")
+    if args.peaks:
+        print(json.dumps({"measured_peaks": peaks}), flush=True)
+        return
     keys = cemu.keygen(cemu.STD, W.KEY_SEED)
-    cemu.set_tuning(keys, fft_gates_per_wg=args.fft_gates_per_wg)
+    cemu.set_tuning(keys, fft_gates_per_wg=args.fft_gates_per_wg, int8_gates_per_wg=args.int8_gates_per_wg,
+                    int8_waves=args.int8_waves)
     B = args.batch
     ops, a, b = W.gate_batch(B, seed=1)
     c1 = keys.encrypt(a, seed=W.ENC_SEED)
@@ -589,13 +607,15 @@ def main():
     dev_outs = {}
     for form in forms:
         out = torch.zeros((B, keys.n + 1), dtype=torch.int32, device=dev)
-        wall, prof = run_form(keys, form, ops_t, pool, ia, ib, out, stream, args.steps, args.warmup)
+        wall, prof, per_step = run_form(keys, form, ops_t, pool, ia, ib, out, stream, args.steps, args.warmup)
         host = out.cpu().numpy().view(np.uint32)
         outs[form] = host
         dev_outs[form] = out
         res[form] = {
             "value": B / (wall / args.steps), "ms_per_step": wall * 1e3 / args.steps,
-            "roofline": roofline(form, prof, B, args.fft_gates_per_wg),
+            "median_ms_per_step": float(np.median(per_step)), "steps_timed": len(per_step),
+            "gates_per_s_at_median_step": B / (float(np.median(per_step)) * 1e-3),
+            "roofline": roofline(form, prof, B, peaks, args.fft_gates_per_wg, args.int8_gates_per_wg, args.int8_waves),
             "key_switch": key_switch_report(prof, B),
             "kernels": {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in prof.items()},
             "decrypt_exact": f"{int(np.sum(keys.decrypt(host) == want))}/{B}",
@@ -622,7 +642,7 @@ def main():
     if tuner is not None and not (args.no_add or args.only):
         from paper_2101_03403_amd.autotune import Autotuner
         tuner_i8 = Autotuner(keys, forms=("int8",))
-    rec_add_int8 = None if (args.no_add or args.only) else add32_latency(keys, dev, "int8", reps=2, tuner=tuner_i8)
+    rec_add_int8 = None if (args.no_add or args.only) else add32_latency(keys, dev, "int8", reps=3, tuner=tuner_i8)
     if rec_add_int8 is not None and tuner_i8 is not None:
         rec_add_int8["form"] = "int8 only, launch shape autotuned per level width"
         rec_add_int8["autotune"] = {str(b): {"choice": [c[0], c[1]], "ms_per_candidate": tuner_i8.measurements.get(b)}
@@ -653,7 +673,8 @@ def main():
         "roofline": primary["roofline"], "cpu_baseline": cpu, "key_switch": primary["key_switch"],
         "kernels": primary["kernels"], "decrypt_exact": primary["decrypt_exact"],
         "output_noise": primary["output_noise"], "noise_chain_level2": primary["noise_chain_level2"],
-        "host_buffers": primary["host_buffers"],
+        "host_buffers": primary["host_buffers"], "measured_peaks": peaks,
+        "median_ms_per_step": primary["median_ms_per_step"],
         "forms": {f: {k: v for k, v in r.items() if k != "kernels"} for f, r in res.items()},
     }
     if rec_add is not None:

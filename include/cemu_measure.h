@@ -1,0 +1,29 @@
+/*
+ * cemu_measure.h -- measurement entry point of libcemu, beside the gate API
+ * of cemu.h: the peak rates that the blind-rotation kernels' fractions of
+ * peak are quoted against, measured on the current device.
+ */
+#ifndef CEMU_MEASURE_H
+#define CEMU_MEASURE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Peak-rate probes on the current HIP device, at the occupancy of the
+ * throughput kernels (one workgroup of eight waves per compute unit):
+ *   fp64_flops_per_s: host double, FP64 fused multiply-adds per second x 2,
+ *     from sixteen independent chains per lane (131,072 iterations each);
+ *   int8_ops_per_s: host double, int8 multiply-adds per second x 2 of
+ *     v_mfma_i32_16x16x64_i8, eight independent accumulators per wave
+ *     (256 iterations each).
+ * Each probe runs once untimed and once timed with hipEvents on hip_stream
+ * (NULL = the default stream); the call waits for them (tens of
+ * milliseconds) and allocates a small device buffer for their results.
+ * Errors: CEMU_ERR_NULL, CEMU_ERR_OOM, CEMU_ERR_HIP. */
+int cemu_measure_peaks(double *fp64_flops_per_s, double *int8_ops_per_s, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CEMU_MEASURE_H */

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcemu.so")
 
-HIP_SOURCES = ["cemu_device.hip", "cemu_br_int8.hip", "cemu_ks.hip", "cemu_br_fft.hip"]
+HIP_SOURCES = ["cemu_device.hip", "cemu_br_int8.hip", "cemu_ks.hip", "cemu_br_fft.hip", "cemu_measure.hip"]
 HOST_SOURCES = ["cemu_host.cpp"]
 
 ARCH = "gfx950"

@@ -57,6 +57,7 @@ EXPORTED = [
     "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_mux", "cemu_bootstrap_level", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
     "cemu_profile_enable", "cemu_profile_read", "cemu_get_tuning", "cemu_set_tuning",
+    "cemu_measure_peaks",
 ]
 PROFILE_KINDS = ["lincomb_modswitch", "blind_rotate_int8", "blind_rotate_fft64", "key_switch"]
 
@@ -83,6 +84,7 @@ def lib() -> C.CDLL:
     L.cemu_phase.argtypes = [vp, C.c_int, vp, i64, vp]
     L.cemu_bootstrap_gates.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_bootstrap_gates_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
+    L.cemu_measure_peaks.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
     L.cemu_blind_rotate_extract.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_key_switch.argtypes = [vp, vp, vp, i64, vp]
     L.cemu_mux.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
@@ -364,6 +366,14 @@ def lwe_constant(n: int, bits, pool_out, dst, stream=None):
     _check(lib().cemu_lwe_constant(n, _dptr(bits, "bits", "u8", rows=cnt),
                                    _dptr(pool_out, "pool_out", "words", width=n + 1),
                                    _dptr(dst, "dst", "rows", rows=cnt), cnt, _stream(stream)))
+
+
+def measure_peaks(stream=None) -> dict:
+    """FP64 FMA and int8 MFMA peak rates of the current GPU at the throughput
+    kernels' occupancy; see cemu_measure_peaks in include/cemu_measure.h."""
+    f, i = C.c_double(), C.c_double()
+    _check(lib().cemu_measure_peaks(C.byref(f), C.byref(i), _stream(stream)))
+    return {"fp64_flops_per_s": f.value, "int8_ops_per_s": i.value}
 
 
 def version() -> str:

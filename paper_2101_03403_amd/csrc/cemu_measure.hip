@@ -1,0 +1,119 @@
+// Peak-rate probes of the two arithmetic units the blind rotation runs on,
+// measured at the occupancy of the throughput kernels (one workgroup of
+// eight waves per compute unit, two waves per SIMD): independent FP64 fused
+// multiply-add chains on the vector ALUs, and independent
+// v_mfma_i32_16x16x64_i8 accumulations on the matrix cores. The kernels'
+// fractions of peak are quoted against these beside the published figures.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/cemu_measure.h"
+#include "cemu_internal.h"
+
+namespace cemu {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int kProbeThreads = 512;
+constexpr int kFmaChains = 16;
+constexpr int kMfmaChains = 8;
+
+// Sixteen independent chains per lane: a <- a * m + c, which stays finite.
+__global__ __launch_bounds__(kProbeThreads, 1) void fp64_fma_probe(double *__restrict__ sink, int iters)
+{
+    const int t = blockIdx.x * kProbeThreads + threadIdx.x;
+    double a[kFmaChains];
+#pragma unroll
+    for (int k = 0; k < kFmaChains; ++k) a[k] = 1.0 + 1e-9 * t + 0.125 * k;
+    const double m = 0.9999999, c = 1e-7;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kFmaChains; ++k) a[k] = fma(a[k], m, c);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kFmaChains; ++k) s += a[k];
+    sink[t] = s;
+}
+
+// Eight independent accumulators per wave, one MFMA each per iteration.
+__global__ __launch_bounds__(kProbeThreads, 1) void int8_mfma_probe(int *__restrict__ sink, int iters)
+{
+    const int t = blockIdx.x * kProbeThreads + threadIdx.x;
+    const v4i a = v4i{t, t + 1, t + 2, t + 3};
+    const v4i b = v4i{3 * t, t ^ 5, t + 7, 11};
+    v4i acc[kMfmaChains];
+#pragma unroll
+    for (int k = 0; k < kMfmaChains; ++k) acc[k] = v4i{k, 0, 0, 0};
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < kMfmaChains; ++k) acc[k] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, acc[k], 0, 0, 0);
+    }
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kMfmaChains; ++k) s += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    sink[t] = s;
+}
+
+std::string msg(const char *what, hipError_t e) { return std::string(what) + ": " + hipGetErrorString(e); }
+
+// Milliseconds of one launch of f, bracketed by events on stream s.
+template <class F>
+int time_launch(hipStream_t s, F &&f, float *ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) {
+        f();
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    return e == hipSuccess ? CEMU_OK : fail(CEMU_ERR_HIP, msg("peak probe", e));
+}
+
+}  // namespace
+}  // namespace cemu
+
+using namespace cemu;
+
+extern "C" int cemu_measure_peaks(double *fp64_flops_per_s, double *int8_ops_per_s, void *hip_stream)
+{
+    clear_error();
+    if (!fp64_flops_per_s || !int8_ops_per_s) return fail(CEMU_ERR_NULL, "NULL result pointer");
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || cus <= 0) return fail(CEMU_ERR_HIP, msg("device query", e));
+    const size_t threads = (size_t)cus * kProbeThreads;
+    void *sink = nullptr;
+    if (hipMalloc(&sink, threads * sizeof(double)) != hipSuccess) return fail(CEMU_ERR_OOM, "probe buffer");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int fma_iters = 1 << 17, mfma_iters = 1 << 8;
+    float ms_fma = 0.f, ms_mfma = 0.f;
+    int rc = CEMU_OK;
+    // one untimed launch of each first (clocks ramp up, code objects load)
+    for (int rep = 0; rep < 2 && rc == CEMU_OK; ++rep) {
+        rc = time_launch(s, [&] {
+            hipLaunchKernelGGL(fp64_fma_probe, dim3(cus), dim3(kProbeThreads), 0, s, (double *)sink, fma_iters);
+        }, &ms_fma);
+        if (rc == CEMU_OK)
+            rc = time_launch(s, [&] {
+                hipLaunchKernelGGL(int8_mfma_probe, dim3(cus), dim3(kProbeThreads), 0, s, (int *)sink, mfma_iters);
+            }, &ms_mfma);
+    }
+    (void)hipFree(sink);
+    if (rc != CEMU_OK) return rc;
+    if (!(ms_fma > 0.f) || !(ms_mfma > 0.f)) return fail(CEMU_ERR_HIP, "peak probe: no elapsed time");
+    *fp64_flops_per_s = 2.0 * kFmaChains * (double)fma_iters * (double)threads / (ms_fma * 1e-3);
+    const double waves = (double)cus * (kProbeThreads / 64);
+    *int8_ops_per_s = 2.0 * 16 * 16 * 64 * kMfmaChains * (double)mfma_iters * waves / (ms_mfma * 1e-3);
+    return CEMU_OK;
+}
