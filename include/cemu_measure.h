@@ -13,13 +13,14 @@ extern "C" {
 /* Peak-rate probes on the current HIP device, at the occupancy of the
  * throughput kernels (one workgroup of eight waves per compute unit):
  *   fp64_flops_per_s: host double, FP64 fused multiply-adds per second x 2,
- *     from sixteen independent chains per lane (131,072 iterations each);
+ *     from sixteen independent chains per lane (65,536 iterations each);
  *   int8_ops_per_s: host double, int8 multiply-adds per second x 2 of
  *     v_mfma_i32_16x16x64_i8, eight independent accumulators per wave
- *     (256 iterations each).
- * Each probe runs once untimed and once timed with hipEvents on hip_stream
- * (NULL = the default stream); the call waits for them (tens of
- * milliseconds) and allocates a small device buffer for their results.
+ *     (16,384 iterations each).
+ * Each probe is launched eight times, alternating, timed with hipEvents on
+ * hip_stream (NULL = the default stream), and its fastest launch counts (the
+ * first ones run while the clocks ramp up from idle). The call waits for
+ * them (about 0.1 s) and allocates a small device buffer for their results.
  * Errors: CEMU_ERR_NULL, CEMU_ERR_OOM, CEMU_ERR_HIP. */
 int cemu_measure_peaks(double *fp64_flops_per_s, double *int8_ops_per_s, void *hip_stream);
 

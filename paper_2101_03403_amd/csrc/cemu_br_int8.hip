@@ -510,15 +510,15 @@ int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint
     }
     // The 16-gate kernel runs one workgroup per CU, so a launch proceeds in
     // rounds of 16 * CUs gates and a round costs the same however few of its
-    // workgroups are busy (75 ms on MI355X). A short tail behind full rounds
-    // goes to the one-gate kernel instead (9.3-10.5 ms per CUs gates): up to
-    // 6 * CUs gates. Outputs do not depend on the shape.
+    // workgroups are busy (75-87 ms on MI355X). A short tail behind full
+    // rounds goes to the one-gate kernel instead (6.2-7.1 ms per CUs gates):
+    // up to 12 * CUs gates. Outputs do not depend on the shape.
     const int64_t cus = ck->num_cus;
     int64_t full = B;
     if (cus > 0) {
         const int64_t round = BR_G * cus;
         const int64_t r = B % round;
-        if (B >= round && r > 0 && r <= 6 * cus) full = B - r;
+        if (B >= round && r > 0 && r <= 12 * cus) full = B - r;
     }
     const int64_t blocks = (full + BR_G - 1) / BR_G;
     hipLaunchKernelGGL((br_int8_kernel<N, WAVES>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, ck->d_bk8, bars, n,

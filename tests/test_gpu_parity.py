@@ -917,7 +917,7 @@ def test_int8_round_tail_split(std, dev):
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     saved = cemu.get_tuning(lk)
     try:
-        for B in (16 * cus + 37, 16 * cus + 6 * cus, 16 * cus + 6 * cus + 1):
+        for B in (16 * cus + 37, 16 * cus + 12 * cus, 16 * cus + 12 * cus + 1):
             say(f"[gpu] int8 tail split: B={B} (CUs {cus})")
             ops, a, b = W.gate_batch(B, seed=400 + B)
             c1 = O.encrypt_bits(ok, a, seed=401)
