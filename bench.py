@@ -40,6 +40,14 @@ PEAK_FP64_FLOPS = 78.6e12        # MI355X FP64 vector, flop/s
 # FP64-FFT form per gate: n steps x (8 FFTs of 512 points at 5 n log2 n + twist
 # 6 x 512, plus 12 x 512 complex multiply-adds at 8 flop).
 FFT_FLOP_PER_GATE = n_ * (8 * (5 * 512 * 9 + 6 * 512) + 12 * 512 * 8)
+# LDS bytes of the FFT throughput kernel (br_fft_kernel<8>) per gate and CMux
+# step, from its structure: 8 transforms x 2 transposes x 8 slots x 16 B x 64
+# lanes written and read; the key spectra of 6 digit rows staged once per
+# workgroup of 8 gates (6 x 16 KiB / 8) and read by every gate (6 x 16 x 16 B
+# x 64); the rotated and own accumulator words read for the digits (2 x 32 x
+# 4 B x 64); the accumulator update (2 x 16 x 4 B x 64 read and written).
+FFT_LDS_WRITE_PER_GATE_STEP = 8 * 2 * 8 * 16 * 64 + 6 * 16384 // 8 + 2 * 16 * 4 * 64
+FFT_LDS_READ_PER_GATE_STEP = 8 * 2 * 8 * 16 * 64 + 6 * 16 * 16 * 64 + 2 * 32 * 4 * 64 + 2 * 16 * 4 * 64
 # Key switch per gate, as the contraction it runs: K = N t base one-hot rows
 # x 640 columns (n + 1 padded) x 4 limbs x 2 ops; and the key bytes a gate's
 # nonzero digits select (3/4 of the N t digits, n + 1 words each).
@@ -530,7 +538,19 @@ def roofline(form, prof, B, peaks, fft_gates_per_wg=8, int8_gates_per_wg=16, int
     ms, cnt = prof["blind_rotate_fft64"]
     avg = ms / max(cnt, 1)
     ach = FFT_FLOP_PER_GATE * B / (avg * 1e-3)
-    return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s",
+    lds = None
+    if fft_gates_per_wg == 8 and "lds_write_bytes_per_s" in peaks:
+        w = FFT_LDS_WRITE_PER_GATE_STEP * n_ * B
+        r = FFT_LDS_READ_PER_GATE_STEP * n_ * B
+        t = w / peaks["lds_write_bytes_per_s"] + r / peaks["lds_read_bytes_per_s"]
+        lds = {"bytes_written_per_launch": w, "bytes_read_per_launch": r,
+               "per_gate_and_step": f"{FFT_LDS_WRITE_PER_GATE_STEP} B written, {FFT_LDS_READ_PER_GATE_STEP} B read",
+               "measured_write_TBps": peaks["lds_write_bytes_per_s"] / 1e12,
+               "measured_read_TBps": peaks["lds_read_bytes_per_s"] / 1e12,
+               "time_at_measured_rates_ms": t * 1e3, "frac_of_kernel_time": t / (avg * 1e-3),
+               "note": "writes and reads of the kernel's own structure at the LDS rates measured on this GPU, "
+                       "serialised: the share of the kernel's time its LDS traffic needs"}
+    return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP64_FLOPS / 1e12, "unit": "TFLOP/s", "lds": lds,
             "frac": ach / PEAK_FP64_FLOPS, "traffic": traffic_bytes("fft64", B) if fft_gates_per_wg == 8 else None,
             "kernel": FFT_KERNEL[fft_gates_per_wg],
             "measured_peak": peaks["fp64_flops_per_s"] / 1e12, "frac_measured": ach / peaks["fp64_flops_per_s"],
@@ -581,8 +601,10 @@ def main():
         print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
         return
     peaks = cemu.measure_peaks()
-    peaks["how"] = ("cemu_measure_peaks on this GPU: independent FP64 FMA chains and int8 MFMA accumulations, "
-                    "one workgroup of 8 waves per compute unit")
+    peaks.update(cemu.measure_lds())
+    peaks["how"] = ("cemu_measure_peaks / cemu_measure_lds on this GPU: independent FP64 FMA chains, int8 MFMA "
+                    "accumulations, and conflict-free 16-byte LDS writes / reads, one workgroup of 8 waves per "
+                    "compute unit, fastest of 8 launches")
     if args.peaks:
         print(json.dumps({"measured_peaks": peaks}), flush=True)
         return

@@ -57,7 +57,7 @@ EXPORTED = [
     "cemu_blind_rotate_extract", "cemu_key_switch", "cemu_mux", "cemu_bootstrap_level", "cemu_lwe_not", "cemu_lwe_copy", "cemu_lwe_constant",
     "cemu_export_keys", "cemu_free_secret_key", "cemu_free_cloud_key", "cemu_last_error", "cemu_version",
     "cemu_profile_enable", "cemu_profile_read", "cemu_get_tuning", "cemu_set_tuning",
-    "cemu_measure_peaks",
+    "cemu_measure_peaks", "cemu_measure_lds",
 ]
 PROFILE_KINDS = ["lincomb_modswitch", "blind_rotate_int8", "blind_rotate_fft64", "key_switch"]
 
@@ -85,6 +85,7 @@ def lib() -> C.CDLL:
     L.cemu_bootstrap_gates.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_bootstrap_gates_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_measure_peaks.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
+    L.cemu_measure_lds.argtypes = [C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
     L.cemu_blind_rotate_extract.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, i64, vp]
     L.cemu_key_switch.argtypes = [vp, vp, vp, i64, vp]
     L.cemu_mux.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp, vp, i64, vp]
@@ -374,6 +375,14 @@ def measure_peaks(stream=None) -> dict:
     f, i = C.c_double(), C.c_double()
     _check(lib().cemu_measure_peaks(C.byref(f), C.byref(i), _stream(stream)))
     return {"fp64_flops_per_s": f.value, "int8_ops_per_s": i.value}
+
+
+def measure_lds(stream=None) -> dict:
+    """LDS write and read bandwidth of the current GPU (bytes/s, all compute
+    units); see cemu_measure_lds in include/cemu_measure.h."""
+    w, r = C.c_double(), C.c_double()
+    _check(lib().cemu_measure_lds(C.byref(w), C.byref(r), _stream(stream)))
+    return {"lds_write_bytes_per_s": w.value, "lds_read_bytes_per_s": r.value}
 
 
 def version() -> str:

@@ -57,6 +57,42 @@ __global__ void int8_mfma_probe(int *__restrict__ sink, int iters)
     sink[t] = s;
 }
 
+// LDS bandwidth at the same occupancy: each lane writes (or reads) eight
+// 16-byte slots per iteration of a 64 KiB buffer, consecutive lanes in
+// consecutive slots (no bank conflicts), the slots moving each iteration.
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+constexpr int kLdsSlots = 4096;   // 16-byte slots, 64 KiB
+
+__global__ void lds_write_probe(double *__restrict__ sink, int iters)
+{
+    __shared__ d2v buf[kLdsSlots];
+    const int tid = threadIdx.x;
+    d2v v = d2v{(double)tid, 1.0};
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) buf[(tid + k * kProbeThreads + 64 * i) & (kLdsSlots - 1)] = v;
+        v.x += 1.0;
+        __asm__ volatile("" ::: "memory");   // keep every store
+    }
+    __syncthreads();
+    sink[blockIdx.x * kProbeThreads + tid] = buf[(tid * 7) & (kLdsSlots - 1)].x;
+}
+
+__global__ void lds_read_probe(unsigned *__restrict__ sink, int iters)
+{
+    __shared__ u4v buf[kLdsSlots];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kLdsSlots; e += kProbeThreads) buf[e] = u4v{(unsigned)e, 1u, 2u, 3u};
+    __syncthreads();
+    u4v acc = u4v{0u, 0u, 0u, 0u};
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc ^= buf[(tid + k * kProbeThreads + 64 * i) & (kLdsSlots - 1)];
+    }
+    sink[blockIdx.x * kProbeThreads + tid] = acc.x ^ acc.y ^ acc.z ^ acc.w;
+}
+
 std::string msg(const char *what, hipError_t e) { return std::string(what) + ": " + hipGetErrorString(e); }
 
 // Milliseconds of one launch of f, bracketed by events on stream s.
@@ -120,5 +156,41 @@ extern "C" int cemu_measure_peaks(double *fp64_flops_per_s, double *int8_ops_per
     *fp64_flops_per_s = 2.0 * kFmaChains * (double)fma_iters * (double)threads / (ms_fma * 1e-3);
     const double waves = (double)cus * (kProbeThreads / 64);
     *int8_ops_per_s = 2.0 * 16 * 16 * 64 * kMfmaChains * (double)mfma_iters * waves / (ms_mfma * 1e-3);
+    return CEMU_OK;
+}
+
+extern "C" int cemu_measure_lds(double *write_bytes_per_s, double *read_bytes_per_s, void *hip_stream)
+{
+    clear_error();
+    if (!write_bytes_per_s || !read_bytes_per_s) return fail(CEMU_ERR_NULL, "NULL result pointer");
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess || cus <= 0) return fail(CEMU_ERR_HIP, msg("device query", e));
+    const size_t threads = (size_t)cus * kProbeThreads;
+    void *sink = nullptr;
+    if (hipMalloc(&sink, threads * sizeof(double)) != hipSuccess) return fail(CEMU_ERR_OOM, "probe buffer");
+    hipStream_t s = (hipStream_t)hip_stream;
+    const int iters = 1 << 12;
+    float ms_w = 0.f, ms_r = 0.f;
+    int rc = CEMU_OK;
+    for (int rep = 0; rep < 8 && rc == CEMU_OK; ++rep) {
+        float t = 0.f;
+        rc = time_launch(s, [&] {
+            hipLaunchKernelGGL(lds_write_probe, dim3(cus), dim3(kProbeThreads), 0, s, (double *)sink, iters);
+        }, &t);
+        if (rc == CEMU_OK && t > 0.f && (ms_w == 0.f || t < ms_w)) ms_w = t;
+        if (rc == CEMU_OK)
+            rc = time_launch(s, [&] {
+                hipLaunchKernelGGL(lds_read_probe, dim3(cus), dim3(kProbeThreads), 0, s, (unsigned *)sink, iters);
+            }, &t);
+        if (rc == CEMU_OK && t > 0.f && (ms_r == 0.f || t < ms_r)) ms_r = t;
+    }
+    (void)hipFree(sink);
+    if (rc != CEMU_OK) return rc;
+    if (!(ms_w > 0.f) || !(ms_r > 0.f)) return fail(CEMU_ERR_HIP, "LDS probe: no elapsed time");
+    const double bytes = 8.0 * 16.0 * (double)iters * (double)threads;
+    *write_bytes_per_s = bytes / (ms_w * 1e-3);
+    *read_bytes_per_s = bytes / (ms_r * 1e-3);
     return CEMU_OK;
 }
