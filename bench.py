@@ -491,8 +491,14 @@ def output_noise(keys, out, want):
     mu = np.where(want == 1, 1 << 29, (1 << 32) - (1 << 29))
     e = (ph - mu) % (1 << 32)
     e = np.where(e >= 1 << 31, e - (1 << 32), e) / float(1 << 32)
+    # closed form for one fixed key (sample variance over the gates): blind
+    # rotation n * 2l * N * (Bg^2 - 1)/12 * sigma_bk^2, key switching
+    # N * t * (9/16) * sigma_ks^2 plus its rounding (N/2) * 2^-32 / 12
+    var_cf = (n_ * 6 * N_ * (128 ** 2 - 1) / 12.0 * 2.0 ** -50 + N_ * KS_T * (9.0 / 16.0) * 2.0 ** -30
+              + (N_ / 2) * 2.0 ** -32 / 12.0)
     return {"std": float(np.std(e)), "max_abs": float(np.max(np.abs(e))), "log2_std": float(np.log2(np.std(e))),
-            "margin": 0.125}
+            "margin": 0.125, "variance": float(np.var(e)), "closed_form_variance": var_cf,
+            "variance_over_closed_form": float(np.var(e)) / var_cf}
 
 
 def noise_chain(keys, form, out1, want1, seed=3):
