@@ -23,9 +23,10 @@
 // the same (slot, lane) order.
 //
 // Throughput kernel: one wave per gate, FG = 8 (default) or 4 gates per
-// workgroup: each wave keeps its accumulator (2 x N u32) and its FFT transpose
-// scratch in LDS; the key spectra of one digit row (16 KiB) are staged in LDS
-// once per workgroup, prefetched through registers one row ahead.
+// workgroup: each wave keeps its accumulator (2 x N u32, as 8-byte records of
+// the coefficient pair (j, j + N/2)) and its FFT transpose scratch in LDS; the
+// key spectra of one digit row (16 KiB) are staged in LDS once per workgroup,
+// prefetched through registers one row ahead.
 //
 // Latency kernel (narrow batches): one gate per workgroup of 6 waves, one
 // wave per gadget digit, so the 6 forward transforms of a step run side by
@@ -333,13 +334,16 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
 {
     constexpr int F_THREADS = 64 * FG;
     constexpr int F_PRE = STAGE_D2 / F_THREADS;   // d2 per thread per stage
-    __shared__ uint32_t acc_all[FG][2][FN];
+    // ACC component c of a gate: record r < N/2 holds (ACC_r, ACC_{r+N/2}),
+    // so a lane reads or updates its coefficient pair (j, j + N/2) with one
+    // 8-byte access, and the rotated pair of a step is one record too
+    __shared__ uint2 acc_all[FG][2][FH];
     __shared__ d2 scr_all[FG][SCR];
     __shared__ d2 kst[STAGE_D2];               // key spectra of the current digit row
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t g = (int64_t)blockIdx.x * FG + wave;
     const bool live = g < B;
-    uint32_t(&acc)[2][FN] = acc_all[wave];
+    uint2(&acc)[2][FH] = acc_all[wave];
     d2 *scr = scr_all[wave];
     const uint16_t *bar = bars + (live ? g : 0) * (int64_t)(n + 1);
     const Tw t0 = make_tw(lane);
@@ -347,10 +351,12 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
 
     // ACC = (0, X^{-bbar} v)
     const uint32_t bb = live ? bar[n] : 0u;
-    for (int m = lane; m < FN; m += 64) {
-        const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * FN - 1);
-        acc[0][m] = 0u;
-        acc[1][m] = tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+    auto tv = [&](uint32_t m) {   // coefficient m < N of X^{-bbar} v
+        return ((m + bb) & (uint32_t)(2 * FN - 1)) < (uint32_t)FN ? 0x20000000u : 0xE0000000u;
+    };
+    for (int r = lane; r < FH; r += 64) {
+        acc[0][r] = uint2{0u, 0u};
+        acc[1][r] = uint2{tv((uint32_t)r), tv((uint32_t)(r + FH))};
     }
 
     d2 pre[F_PRE];
@@ -368,19 +374,24 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
         });
 #pragma unroll 1
         for (int c = 0; c < 2; ++c) {
-            // D = X^a ACC_c - ACC_c at this lane's 16 coefficients (+ digit offset, field top bits flipped)
+            // D = X^a ACC_c - ACC_c at this lane's 16 coefficients (+ digit offset, field top bits flipped).
+            // Coefficients j and j + N/2 of X^a ACC come from ACC at t = j - a and
+            // t + N/2 (mod 2N), which share the record t mod N/2; the quadrant
+            // t / (N/2) says which half each takes and which are negated
+            // (X^N = -1): (v0, v1) = (x, y), (y, -x), (-x, -y), (-y, x).
             uint32_t dlo[8], dhi[8];
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const uint32_t j = (uint32_t)(lane + 64 * m + h * FH);
-                    const uint32_t tt = (j - a) & (uint32_t)(2 * FN - 1);
-                    uint32_t v = acc[c][tt & (uint32_t)(FN - 1)];
-                    v = (tt & (uint32_t)FN) ? 0u - v : v;
-                    const uint32_t d = (v - acc[c][j] + kDigitOffset) ^ kDigitSignBits;
-                    if (h == 0) dlo[m] = d; else dhi[m] = d;
-                }
+                const uint32_t j = (uint32_t)(lane + 64 * m);
+                const uint32_t tt = (j - a) & (uint32_t)(2 * FN - 1);
+                const uint32_t quad = tt / FH;
+                const uint2 rr = acc[c][tt & (uint32_t)(FH - 1)];
+                const uint2 pl = acc[c][j];
+                const uint32_t f = (quad & 1u) ? rr.y : rr.x, sc = (quad & 1u) ? rr.x : rr.y;
+                const uint32_t v0 = (quad == 2u || quad == 3u) ? 0u - f : f;
+                const uint32_t v1 = (quad == 1u || quad == 2u) ? 0u - sc : sc;
+                dlo[m] = (v0 - pl.x + kDigitOffset) ^ kDigitSignBits;
+                dhi[m] = (v1 - pl.y + kDigitOffset) ^ kDigitSignBits;
             });
 #pragma unroll 1
             for (int jj = 0; jj < 3; ++jj) {
@@ -423,14 +434,16 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
         }
         // inverse transforms, untwist, round, accumulate (this wave's ACC only)
         wave_lds_fence();
-        auto finish = [&](d2 (&x)[8], uint32_t *dst) {
+        auto finish = [&](d2 (&x)[8], uint2 *dst) {
             fft_inv(x, scr, lane, t);
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
                 const d2 y = cmul(x[m], cconj(twist_slot(m)));
                 const int j = lane + 64 * m;
-                dst[j] += round_mod32(y.x);
-                dst[j + FH] += round_mod32(y.y);
+                uint2 v = dst[j];
+                v.x += round_mod32(y.x);
+                v.y += round_mod32(y.y);
+                dst[j] = v;
             });
         };
         if (wave >= FG / 2) __builtin_amdgcn_s_setprio(1);   // issue balance, first inverse
@@ -444,11 +457,12 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
     // sample extraction
     if (live) {
         uint32_t *e = ext + g * (FN + 1);
+        auto coef = [&](int q, int k) { return k < FH ? acc[q][k].x : acc[q][k - FH].y; };
         for (int j = lane; j <= FN; j += 64) {
             uint32_t v;
-            if (j == 0) v = acc[0][0];
-            else if (j == FN) v = acc[1][0];
-            else v = 0u - acc[0][FN - j];
+            if (j == 0) v = coef(0, 0);
+            else if (j == FN) v = coef(1, 0);
+            else v = 0u - coef(0, FN - j);
             e[j] = v;
         }
     }
