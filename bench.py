@@ -64,8 +64,8 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 # comments and whitespace removed, so that comment edits keep it), else
 # reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "a41677799a2d2978",
-              "bytes": 486_921 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
+    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "40698d6ef89fcdb3",
+              "bytes": 486_905 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
     "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "61f61386898756f1",
              "bytes": 245_648 * 1024 * 2 + 17_936 * 1024, "batch": 4096},
     # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
