@@ -270,88 +270,85 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
     }
 }
 
-// Residue-class tiling of the 16-gate product (8 waves). Wave v owns the
-// output rows m = v (mod 8) of both components: tile (q, u) is rows
-// 128 u + v + 8 r', r' = 0..15, of component q, and the wave's K range is
-// shifted by c = (v + 1) mod 8, i.e. K-tile b is columns 64 b + c .. + 63.
+// Residue-class tiling of the 16-gate product (8 waves). Wave w computes
+// output component q = w / 4 and, of it, the rows m = v (mod 4), v = w % 4:
+// tile u is rows 64 u + v + 4 r', r' = 0..15, and the wave's K range is
+// shifted by c = (v + 1) mod 4, i.e. K-tile b is columns 64 b + c .. + 63.
 // A lane (row r', K-group g4) then needs the 16 bytes of R starting at
-//   N - 1 - m + k = N - 8 r' + 16 g4 + 64 (b - 2 u) - 8 [v = 7],
-// an 8-byte boundary, so a fragment is two aligned 8-byte reads and needs
-// no byte alignment; and it depends on b - 2 u only, so one fragment serves
-// every (u, b) pair on that diagonal: 256 MFMAs per 60 fragments (N = 1024)
+//   N - 1 - m + k = N - 4 r' + 16 g4 + 64 (b - u) - 4 [v = 3],
+// a dword boundary, so a fragment is four whole dwords with no byte
+// alignment; and it depends on b - u only, so one fragment serves every
+// (u, b) pair on that diagonal: 256 MFMAs per 31 fragments (N = 1024)
 // against 76 with blocks of consecutive rows. The columns shifted past N
 // wrap around: column N + k' (k' < c <= v <= m) meets R[2N - 1 - m + k'] =
 // -T[m][k'], so it is fed the negated digit -d[k'] (digits are in [-64, 64),
 // so their negations fit a signed byte).
 //
 // ACC row m of a gate is kept at the permuted position
-//   P(m) = (m & ~31) | ((m & 7) << 2) | ((m >> 3) & 3)
+//   P(m) = (m & ~15) | ((m & 3) << 2) | ((m >> 2) & 3)
 // (then XOR-swizzled by gate as in br_int8_kernel), which puts the four rows
-// 8 apart that one lane of an MFMA tile holds into one 16-byte group, and the
-// coefficients i and i + 8 of a 16-coefficient digit chunk into one 8-byte
-// pair.
+// 4 apart that one lane of an MFMA tile holds into one 16-byte group, and
+// keeps each 16-coefficient digit chunk in four 16-byte groups.
 template <int N>
-struct S8Shape {
+struct ResShape {
     static constexpr int THREADS = 512;
-    static constexpr int U = N / 128;              // 128-row blocks per component
-    static constexpr int MT = 2 * U;               // tiles per wave: (q, u)
+    static constexpr int MT = N / 64;              // tiles per wave (64-row blocks of one component)
     static constexpr int KT = N / 64;              // 64-wide K-tiles
-    static constexpr int DLO = -2 * (U - 1);       // lowest diagonal b - 2u
-    static constexpr int NDELTA = KT + 2 * (U - 1);
+    static constexpr int DLO = -(MT - 1);          // lowest diagonal b - u
+    static constexpr int NDELTA = KT + MT - 1;
     static constexpr int RB = 2 * N;
     static constexpr int STAGE_BYTES = 2 * 4 * RB;
     static constexpr int PRE = STAGE_BYTES / (THREADS * 16);
     static constexpr int CHUNKS = BR_G * N / 16;
     static constexpr int CPT = CHUNKS / THREADS;
-    static_assert(U >= 1 && PRE >= 1 && CPT >= 1, "shape");
+    static_assert(MT >= 1 && PRE >= 1 && CPT >= 1, "shape");
 };
 
-__device__ __forceinline__ uint32_t s8_perm(uint32_t m) { return (m & ~31u) | ((m & 7u) << 2) | ((m >> 3) & 3u); }
+__device__ __forceinline__ uint32_t res_perm(uint32_t m) { return (m & ~15u) | ((m & 3u) << 2) | ((m >> 2) & 3u); }
 
 // Bytes of a packed word of signed digits, negated: with b = x ^ 0x80 = d + 128
 // in [64, 191] per byte, ~b + 1 = 128 - d stays inside its byte.
 __device__ __forceinline__ uint32_t neg_digits(uint32_t x) { return ((~(x ^ 0x80808080u)) + 0x01010101u) ^ 0x80808080u; }
 
-// acc[q U + u] += T_tile(q, u, b) * D_tile(b), one limb of component q; pr
-// points at the lane's first fragment (diagonal DLO), 8 uint2 per diagonal.
-template <int N, int Q>
-__device__ __forceinline__ void s8_block(const uint2 *__restrict__ pr, v4i (&acc)[S8Shape<N>::MT],
-                                         const v4i (&bf)[S8Shape<N>::KT])
+// acc[u] += T_tile(u, b) * D_tile(b), one limb; pr points at the lane's first
+// fragment (diagonal DLO), 16 dwords per diagonal.
+template <int N>
+__device__ __forceinline__ void res_block(const uint32_t *__restrict__ pr, v4i (&acc)[ResShape<N>::MT],
+                                          const v4i (&bf)[ResShape<N>::KT])
 {
-    using S = S8Shape<N>;
+    using S = ResShape<N>;
     // Software pipeline: fragment di + 1 is requested before the MFMAs of
     // fragment di are issued; sched_barrier keeps that order.
-    uint2 f0 = pr[0], f1 = pr[1];
+    v4i fr = v4i{(int)pr[0], (int)pr[1], (int)pr[2], (int)pr[3]};
     static_for<0, S::NDELTA>([&](auto dI) {
         constexpr int di = decltype(dI)::value;
-        const v4i fr = v4i{(int)f0.x, (int)f0.y, (int)f1.x, (int)f1.y};
-        if constexpr (di + 1 < S::NDELTA) {
-            f0 = pr[8 * (di + 1)];
-            f1 = pr[8 * (di + 1) + 1];
-        }
-        static_for<0, S::U>([&](auto uI) {
+        v4i nx = fr;
+        if constexpr (di + 1 < S::NDELTA)
+            nx = v4i{(int)pr[16 * di + 16], (int)pr[16 * di + 17], (int)pr[16 * di + 18], (int)pr[16 * di + 19]};
+        static_for<0, S::MT>([&](auto uI) {
             constexpr int u = decltype(uI)::value;
-            constexpr int b = di + S::DLO + 2 * u;
-            if constexpr (b >= 0 && b < S::KT)
-                acc[Q * S::U + u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[Q * S::U + u], 0, 0, 0);
+            constexpr int b = di + S::DLO + u;
+            if constexpr (b >= 0 && b < S::KT) acc[u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[u], 0, 0, 0);
         });
+        fr = nx;
         __builtin_amdgcn_sched_barrier(0);
     });
 }
 
 template <int N>
-__global__ __launch_bounds__(512, 1) void br_int8_s8_kernel(const uint8_t *__restrict__ bk8,
-                                                            const uint16_t *__restrict__ bars, int32_t n, int64_t B,
-                                                            uint32_t *__restrict__ ext)
+__global__ __launch_bounds__(512, 1) void br_int8_res_kernel(const uint8_t *__restrict__ bk8,
+                                                             const uint16_t *__restrict__ bars, int32_t n, int64_t B,
+                                                             uint32_t *__restrict__ ext)
 {
-    using S = S8Shape<N>;
+    using S = ResShape<N>;
     __shared__ __attribute__((aligned(16))) uint32_t acc_s[2][BR_G * N];
     __shared__ __attribute__((aligned(16))) uint8_t dig[BR_G * N];
     __shared__ __attribute__((aligned(16))) uint32_t rst[S::STAGE_BYTES / 4];
 
-    const int tid = threadIdx.x, lane = tid & 63, v = tid >> 6;   // wave = row residue class
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int q = wave >> 2, v = wave & 3;                        // output component, row residue
     const int gl = lane & 15, g4 = lane >> 4;
-    const int c = (v + 1) & 7;                                     // K shift of this wave
+    const int c = (v + 1) & 3;                                     // K shift of this wave
     const int64_t g0 = (int64_t)blockIdx.x * BR_G;
     const int64_t barrow = (int64_t)n + 1;
     const bool live = g0 + gl < B;
@@ -363,13 +360,14 @@ __global__ __launch_bounds__(512, 1) void br_int8_s8_kernel(const uint8_t *__res
         const int g = e / N, m = e - (e / N) * N;
         const uint32_t bb = (g0 + g < B) ? (uint32_t)bars[(g0 + g) * barrow + n] : 0u;
         const uint32_t tt = ((uint32_t)m + bb) & (uint32_t)(2 * N - 1);
-        const uint32_t ph = (uint32_t)(g * N) + (s8_perm((uint32_t)m) ^ acc_swz(g));
+        const uint32_t ph = (uint32_t)(g * N) + (res_perm((uint32_t)m) ^ acc_swz(g));
         acc_s[0][ph] = 0u;
         acc_s[1][ph] = tt < (uint32_t)N ? 0x20000000u : 0xE0000000u;
     }
 
-    // The lane's first fragment: byte N - 8 r' + 16 g4 - 8 [v = 7] + 64 DLO >= 0 of R.
-    const int frag_byte = N - 8 * gl + 16 * g4 - (v == 7 ? 8 : 0) + 64 * S::DLO;
+    // The lane's first fragment: byte N - 4 r' + 16 g4 - 4 [v = 3] + 64 DLO >= 0
+    // of R (a dword boundary), in the limb sequences of component q.
+    const int frag_dw = (N - 4 * gl + 16 * g4 - (v == 3 ? 4 : 0) + 64 * S::DLO) / 4 + q * 4 * (S::RB / 4);
 
     // Register-staged prefetch of the next digit row's key limbs.
     u4 pre[S::PRE];
@@ -413,31 +411,25 @@ __global__ __launch_bounds__(512, 1) void br_int8_s8_kernel(const uint8_t *__res
                 for (int r = 0; r < S::CPT; ++r) {
                     const int ch = (tid + r * S::THREADS) >> 4;
                     const int k0 = 16 * ch;
-                    // coefficients t and t + 8 of the chunk share an 8-byte pair, so
-                    // the words of coefficients 4h .. 4h + 3 and 8 + 4h .. are built together
-                    const uint32_t pbase = (uint32_t)(32 * (ch >> 1) + 2 * (ch & 1));
-                    uint32_t packed[4];
+                    // 16-byte group e4 of the chunk holds coefficients e4, 4 + e4, 8 + e4, 12 + e4
+                    uint32_t packed[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        uint32_t word[2] = {0u, 0u};
+                    for (int e4 = 0; e4 < 4; ++e4) {
+                        const u4 uw = *reinterpret_cast<const u4 *>(row + (((uint32_t)(k0 + 4 * e4)) ^ myswz));
+                        const uint32_t un[4] = {uw.x, uw.y, uw.z, uw.w};
 #pragma unroll
-                        for (int e4 = 0; e4 < 4; ++e4) {
-                            const int t = 4 * h + e4;
-                            const uint2 pw = *reinterpret_cast<const uint2 *>(row + ((pbase + 4u * (uint32_t)t) ^ myswz));
-#pragma unroll
-                            for (int hi = 0; hi < 2; ++hi) {
-                                const uint32_t k = (uint32_t)(k0 + t + 8 * hi);
-                                const uint32_t tt = (k - a_cur) & (uint32_t)(2 * N - 1);
-                                uint32_t vv = row[s8_perm(tt & (uint32_t)(N - 1)) ^ myswz];
-                                vv = (tt & (uint32_t)N) ? 0u - vv : vv;
-                                const uint32_t y = vv - (hi ? pw.y : pw.x) + kDigitOffset;
-                                word[hi] |= ((y >> sh) & 127u) << (8 * e4);
-                            }
+                        for (int d = 0; d < 4; ++d) {
+                            const uint32_t k = (uint32_t)(k0 + 4 * d + e4);
+                            const uint32_t tt = (k - a_cur) & (uint32_t)(2 * N - 1);
+                            uint32_t vv = row[res_perm(tt & (uint32_t)(N - 1)) ^ myswz];
+                            vv = (tt & (uint32_t)N) ? 0u - vv : vv;
+                            const uint32_t y = vv - un[d] + kDigitOffset;
+                            packed[d] |= ((y >> sh) & 127u) << (8 * e4);
                         }
-                        // bytes x in [0,128) hold digit + 64; (x + 64) ^ 0x80 = x - 64 mod 256, no carries
-                        packed[h] = (word[0] + 0x40404040u) ^ 0x80808080u;
-                        packed[h + 2] = (word[1] + 0x40404040u) ^ 0x80808080u;
                     }
+                    // bytes x in [0,128) hold digit + 64; (x + 64) ^ 0x80 = x - 64 mod 256, no carries
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) packed[d] = (packed[d] + 0x40404040u) ^ 0x80808080u;
                     *reinterpret_cast<u4 *>(dig + dig_off(N, gl, ch)) = u4{packed[0], packed[1], packed[2], packed[3]};
                 }
             }
@@ -454,12 +446,9 @@ __global__ __launch_bounds__(512, 1) void br_int8_s8_kernel(const uint8_t *__res
                 if constexpr (b == S::KT - 1) {
                     if (g4 == 3) hi = u4{neg_digits(hi.x), neg_digits(hi.y), neg_digits(hi.z), neg_digits(hi.w)};
                 }
-                const bool up = c >= 4;   // wave-uniform
-                const uint32_t w0 = up ? lo.y : lo.x, w1 = up ? lo.z : lo.y, w2 = up ? lo.w : lo.z;
-                const uint32_t w3 = up ? hi.x : lo.w, w4 = up ? hi.y : hi.x;
-                const uint32_t s = (uint32_t)(c & 3);
-                bf[b] = v4i{(int)__builtin_amdgcn_alignbyte(w1, w0, s), (int)__builtin_amdgcn_alignbyte(w2, w1, s),
-                            (int)__builtin_amdgcn_alignbyte(w3, w2, s), (int)__builtin_amdgcn_alignbyte(w4, w3, s)};
+                const uint32_t s = (uint32_t)c;
+                bf[b] = v4i{(int)__builtin_amdgcn_alignbyte(lo.y, lo.x, s), (int)__builtin_amdgcn_alignbyte(lo.z, lo.y, s),
+                            (int)__builtin_amdgcn_alignbyte(lo.w, lo.z, s), (int)__builtin_amdgcn_alignbyte(hi.x, lo.w, s)};
             });
 
             v4i acc[S::MT];
@@ -467,31 +456,28 @@ __global__ __launch_bounds__(512, 1) void br_int8_s8_kernel(const uint8_t *__res
             // Issue balance: waves w and w + 4 share a SIMD and do the same
             // work; the arbiter issues the older one first, so the younger
             // raises its priority for the first three of the four limb passes.
-            if (v >= 4) __builtin_amdgcn_s_setprio(1);
+            if (wave >= 4) __builtin_amdgcn_s_setprio(1);
 #pragma unroll 1
             for (int kappa = 3; kappa >= 0; --kappa) {
                 if (kappa == 0) __builtin_amdgcn_s_setprio(0);
                 if (kappa != 3) static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] <<= 8; });
-                const uint8_t *base = reinterpret_cast<const uint8_t *>(rst) + frag_byte;
-                s8_block<N, 0>(reinterpret_cast<const uint2 *>(base + (0 * 4 + kappa) * S::RB), acc, bf);
-                s8_block<N, 1>(reinterpret_cast<const uint2 *>(base + (1 * 4 + kappa) * S::RB), acc, bf);
+                res_block<N>(rst + frag_dw + kappa * (S::RB / 4), acc, bf);
             }
             static_for<0, S::MT>([&](auto tI) { total[decltype(tI)::value] += acc[decltype(tI)::value]; });
         }
         __syncthreads();  // every wave has finished reading ACC for this step
-        // lane (gl, g4) of tile (q, u) holds rows 128 u + 32 g4 + 8 e + v, e = 0..3,
-        // which P puts at 128 u + 32 g4 + 4 v + e; the swizzle touches bits 2..5
-        // only, so the tiles of a lane are 128 u apart
-        const uint32_t upd = (uint32_t)(gl * N) + ((uint32_t)(32 * g4 + 4 * v) ^ myswz);
+        // lane (gl, g4) of tile u holds rows 64 u + 16 g4 + 4 e + v, e = 0..3,
+        // which P puts at 64 u + 16 g4 + 4 v + e; the swizzle touches bits 2..5
+        // only, so the tiles of a lane are 64 u apart
+        const uint32_t upd = (uint32_t)(gl * N) + ((uint32_t)(16 * g4 + 4 * v) ^ myswz);
         static_for<0, S::MT>([&](auto tI) {
-            constexpr int t = decltype(tI)::value;
-            constexpr int q = t / S::U, u = t - q * S::U;
-            u4 *ptr = reinterpret_cast<u4 *>(&acc_s[q][upd + 128 * u]);
+            constexpr int u = decltype(tI)::value;
+            u4 *ptr = reinterpret_cast<u4 *>(&acc_s[q][upd + 64 * u]);
             u4 w = *ptr;
-            w.x += (uint32_t)total[t][0];
-            w.y += (uint32_t)total[t][1];
-            w.z += (uint32_t)total[t][2];
-            w.w += (uint32_t)total[t][3];
+            w.x += (uint32_t)total[u][0];
+            w.y += (uint32_t)total[u][1];
+            w.z += (uint32_t)total[u][2];
+            w.w += (uint32_t)total[u][3];
             *ptr = w;
         });
         a_cur = a_next;
@@ -504,9 +490,9 @@ __global__ __launch_bounds__(512, 1) void br_int8_s8_kernel(const uint8_t *__res
         if (g0 + g >= B) continue;
         const uint32_t base = (uint32_t)(g * N), sw = acc_swz(g);
         uint32_t val;
-        if (jj == 0) val = acc_s[0][base + (s8_perm(0u) ^ sw)];
-        else if (jj == N) val = acc_s[1][base + (s8_perm(0u) ^ sw)];
-        else val = 0u - acc_s[0][base + (s8_perm((uint32_t)(N - jj)) ^ sw)];
+        if (jj == 0) val = acc_s[0][base + (res_perm(0u) ^ sw)];
+        else if (jj == N) val = acc_s[1][base + (res_perm(0u) ^ sw)];
+        else val = 0u - acc_s[0][base + (res_perm((uint32_t)(N - jj)) ^ sw)];
         ext[(g0 + g) * (N + 1) + jj] = val;
     }
 }
@@ -763,7 +749,7 @@ int launch_shape(const cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint
     }
     const int64_t blocks = (full + BR_G - 1) / BR_G;
     if constexpr (WAVES == 8)
-        hipLaunchKernelGGL((br_int8_s8_kernel<N>), dim3((unsigned)blocks), dim3(512), 0, s, ck->d_bk8, bars, n, full, ext);
+        hipLaunchKernelGGL((br_int8_res_kernel<N>), dim3((unsigned)blocks), dim3(512), 0, s, ck->d_bk8, bars, n, full, ext);
     else
         hipLaunchKernelGGL((br_int8_kernel<N, WAVES>), dim3((unsigned)blocks), dim3(64 * WAVES), 0, s, ck->d_bk8, bars,
                            n, full, ext);
