@@ -66,8 +66,8 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 TRAFFIC = {
     "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "40698d6ef89fcdb3",
               "bytes": 486_905 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
-    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "61f61386898756f1",
-             "bytes": 245_648 * 1024 * 2 + 17_936 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "95683cb5d85f7720",
+             "bytes": 245_746 * 1024 * 2 + 18_448 * 1024, "batch": 4096},
     # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
     "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "8f9eb8b89663227d",
            "bytes": (274 + 383_248) * 1024 * 2 + (10_096 + 29_152) * 1024, "batch": 4096},
@@ -529,8 +529,10 @@ def noise_chain(keys, form, out1, want1, seed=3):
 
 def roofline(form, prof, B, peaks, fft_gates_per_wg=8, int8_gates_per_wg=16, int8_waves=8):
     if form == "int8":
-        kname = (f"br_int8_kernel<1024, {int8_waves}>" if int8_gates_per_wg == 16
-                 else f"br_int8_lat_kernel<1024, {int8_waves}>")
+        if int8_gates_per_wg == 16:
+            kname = "br_int8_res_kernel<1024>" if int8_waves == 8 else "br_int8_kernel<1024, 4>"
+        else:
+            kname = f"br_int8_lat_kernel<1024, {int8_waves}>"
         default_shape = int8_gates_per_wg == 16 and int8_waves == 8
         ms, cnt = prof["blind_rotate_int8"]
         avg = ms / max(cnt, 1)

@@ -17,16 +17,19 @@
 // The Toeplitz A operand is never materialised. For output rows m and
 // columns k, T[m][k] = R[N-1-m+k] with R the reversed, sign-extended limb
 // sequence of the key (see cemu_internal.h), so a lane's 16 A bytes are 16
-// consecutive bytes of R, fetched as 5 aligned dwords from LDS and shifted
-// with v_alignbyte. A 16x64 tile of T depends only on (k0 - m0), so each
-// generated fragment is reused for every (M-tile, K-tile) pair on that
-// diagonal: MT*KT / NDELTA = 512/92 (N = 1024) MFMAs per generated fragment.
+// consecutive bytes of R. A tile of T depends only on the difference of its
+// row and column offsets, so each generated fragment is reused for every
+// (M-tile, K-tile) pair on that diagonal.
 //
 // Per digit row p the workgroup first computes the digits of all 16 gates
 // into LDS (each digit once), then every wave loads its B operand from there.
-// Waves: WAVES per workgroup; the first half computes output component A,
-// the second half B, each wave a contiguous block of rows, and each keeps
-// the step's running sum in registers until the accumulators are updated.
+// The first half of the waves computes output component A, the second half
+// B, and each keeps the step's running sum in registers until the
+// accumulators are updated. Two tilings: br_int8_res_kernel (8 waves, the
+// default) gives each wave the rows of one residue class mod 4, which makes
+// every fragment four whole dwords (see there); br_int8_kernel (the 4-wave
+// shape) gives each wave a block of consecutive rows, whose fragments start
+// at any byte and are fetched as 5 dwords and shifted with v_alignbyte.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
