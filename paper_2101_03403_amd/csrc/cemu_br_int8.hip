@@ -314,8 +314,10 @@ __device__ __forceinline__ uint32_t res_perm(uint32_t m) { return (m & ~15u) | (
 __device__ __forceinline__ uint32_t neg_digits(uint32_t x) { return ((~(x ^ 0x80808080u)) + 0x01010101u) ^ 0x80808080u; }
 
 // acc[u] += T_tile(u, b) * D_tile(b), one limb; pr points at the lane's first
-// fragment (diagonal DLO), 16 dwords per diagonal.
-template <int N>
+// fragment (diagonal DLO), 16 dwords per diagonal. FRESH: acc holds nothing
+// yet, so each tile's first product (b = 0, the first in diagonal order)
+// starts from zero instead of reading acc.
+template <int N, bool FRESH = false>
 __device__ __forceinline__ void res_block(const uint32_t *__restrict__ pr, v4i (&acc)[ResShape<N>::MT],
                                           const v4i (&bf)[ResShape<N>::KT])
 {
@@ -331,7 +333,9 @@ __device__ __forceinline__ void res_block(const uint32_t *__restrict__ pr, v4i (
         static_for<0, S::MT>([&](auto uI) {
             constexpr int u = decltype(uI)::value;
             constexpr int b = di + S::DLO + u;
-            if constexpr (b >= 0 && b < S::KT) acc[u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[u], 0, 0, 0);
+            if constexpr (b >= 0 && b < S::KT)
+                acc[u] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], (FRESH && b == 0) ? v4i{0, 0, 0, 0} : acc[u],
+                                                               0, 0, 0);
         });
         fr = nx;
         __builtin_amdgcn_sched_barrier(0);
@@ -454,19 +458,25 @@ __global__ __launch_bounds__(512, 1) void br_int8_res_kernel(const uint8_t *__re
                             (int)__builtin_amdgcn_alignbyte(lo.w, lo.z, s), (int)__builtin_amdgcn_alignbyte(hi.x, lo.w, s)};
             });
 
+            // Horner over the limbs: acc = (C3 * 2^8 + C2) * 2^8 + C1, then the
+            // last limb's products are accumulated straight onto
+            // total + acc * 2^8. Issue balance: waves w and w + 4 share a SIMD
+            // and do the same work; the arbiter issues the older one first, so
+            // the younger raises its priority for the first three limb passes.
             v4i acc[S::MT];
-            static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] = v4i{0, 0, 0, 0}; });
-            // Issue balance: waves w and w + 4 share a SIMD and do the same
-            // work; the arbiter issues the older one first, so the younger
-            // raises its priority for the first three of the four limb passes.
             if (wave >= 4) __builtin_amdgcn_s_setprio(1);
+            res_block<N, true>(rst + frag_dw + 3 * (S::RB / 4), acc, bf);
 #pragma unroll 1
-            for (int kappa = 3; kappa >= 0; --kappa) {
-                if (kappa == 0) __builtin_amdgcn_s_setprio(0);
-                if (kappa != 3) static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] <<= 8; });
+            for (int kappa = 2; kappa >= 1; --kappa) {
+                static_for<0, S::MT>([&](auto tI) { acc[decltype(tI)::value] <<= 8; });
                 res_block<N>(rst + frag_dw + kappa * (S::RB / 4), acc, bf);
             }
-            static_for<0, S::MT>([&](auto tI) { total[decltype(tI)::value] += acc[decltype(tI)::value]; });
+            __builtin_amdgcn_s_setprio(0);
+            static_for<0, S::MT>([&](auto tI) {
+                constexpr int t = decltype(tI)::value;
+                total[t] += acc[t] << 8;
+            });
+            res_block<N>(rst + frag_dw, total, bf);
         }
         __syncthreads();  // every wave has finished reading ACC for this step
         // lane (gl, g4) of tile u holds rows 64 u + 16 g4 + 4 e + v, e = 0..3,
