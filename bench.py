@@ -611,7 +611,7 @@ def main():
     peaks = cemu.measure_peaks()
     peaks.update(cemu.measure_lds())
     peaks["how"] = ("cemu_measure_peaks / cemu_measure_lds on this GPU: independent FP64 FMA chains, int8 MFMA "
-                    "accumulations, and conflict-free 16-byte LDS writes / reads, one workgroup of 8 waves per "
+                    "accumulations, and conflict-free 16-byte LDS writes / reads at immediate offsets, one workgroup of 8 waves per "
                     "compute unit, fastest of 8 launches")
     if args.peaks:
         print(json.dumps({"measured_peaks": peaks}), flush=True)

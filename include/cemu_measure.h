@@ -25,11 +25,12 @@ extern "C" {
 int cemu_measure_peaks(double *fp64_flops_per_s, double *int8_ops_per_s, void *hip_stream);
 
 /* LDS bandwidth of the current HIP device, summed over its compute units, at
- * the same occupancy: every lane writes (write_bytes_per_s), or reads
- * (read_bytes_per_s), eight 16-byte slots per iteration of a 64 KiB LDS
- * buffer, consecutive lanes in consecutive slots (no bank conflicts), 4,096
- * iterations. Timing, repetitions and errors as cemu_measure_peaks. The FFT
- * kernels' LDS traffic is quoted against these. */
+ * the same occupancy: every wave writes (write_bytes_per_s), or reads
+ * (read_bytes_per_s), its own 8 KiB region of a 64 KiB LDS buffer as eight
+ * rows of 64 consecutive 16-byte slots per iteration (no bank conflicts;
+ * per-lane base plus immediate offsets, no address arithmetic between the
+ * accesses), 4,096 iterations. Timing, repetitions and errors as
+ * cemu_measure_peaks. The FFT kernels' LDS traffic is quoted against these. */
 int cemu_measure_lds(double *write_bytes_per_s, double *read_bytes_per_s, void *hip_stream);
 
 #ifdef __cplusplus

@@ -28,13 +28,13 @@
 // key spectra of one digit row (16 KiB) are staged in LDS once per workgroup,
 // prefetched through registers one row ahead.
 //
-// Latency kernel (narrow batches): one gate per workgroup of 6 waves, one
-// wave per gadget digit, so the 6 forward transforms of a step run side by
-// side; each digit wave multiplies its spectrum by its own two key spectra
-// (prefetched into registers a step ahead), the partial products meet in
-// LDS, all six waves sum them (in a fixed row order, each wave a share of
-// the frequency slots), and two waves run the two inverse transforms. A step
-// then costs about three transform latencies instead of eight.
+// Latency kernel (narrow batches): one gate per workgroup of 8 waves. Six
+// waves, one per gadget digit, run the 6 forward transforms of a step side
+// by side and leave their spectra in LDS; every wave then forms, for one
+// frequency slot, both outputs' sums over the six rows (in a fixed row
+// order, its key values prefetched into registers a step ahead), and two
+// waves run the two inverse transforms. A step then costs about three
+// transform latencies instead of eight.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -468,9 +468,7 @@ __global__ __launch_bounds__(64 * FG, 1) void br_fft_kernel(const d2 *__restrict
     }
 }
 
-constexpr int LAT_WAVES = 6;   // one wave per digit row (2 components x l = 3)
-
-constexpr int LAT_REGION = 2 * FH;  // d2 per wave: its two partial products, or its transpose scratch
+constexpr int LAT_WAVES = 8;   // six digit-row waves and two inverse waves; all eight reduce
 
 // ACC component c is kept as one 16-byte record per coefficient pair
 // (j, j + N/2), j < N/2: (R_j, R_{j+N/2}, ACC_j, ACC_{j+N/2}) with
@@ -481,22 +479,32 @@ constexpr int LAT_REGION = 2 * FH;  // d2 per wave: its two partial products, or
 // at k = (j + a) mod 2N and k + N/2, i.e. in one record r = k mod N/2, as
 // (f, s) = (v0, v1), (-v1, v0), (-v0, -v1) or (v1, -v0) for k / (N/2) =
 // 0, 1, 2, 3 (negacyclic wrap).
+//
+// A step: waves 0..5 (digit row p = wave) decompose and transform their
+// digit row and write its spectrum to their region; then every wave w takes
+// frequency slot w of all six spectra and forms both outputs' sums
+// sum_p X_p K_{p,q} there (its twelve key values prefetched a step ahead);
+// then waves 6 and 7 run the inverse transforms of outputs 0 and 1. Only
+// the spectra (8 KiB per row) and the sums cross LDS, not per-row products.
 __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 *__restrict__ spec,
                                                                       const uint16_t *__restrict__ bars, int32_t n,
                                                                       uint32_t *__restrict__ ext)
 {
-    static_assert(SCR <= LAT_REGION, "scratch fits a region");
+    static_assert(FH <= SCR, "a spectrum fits a region");
     __shared__ __attribute__((aligned(16))) uint32_t zacc[2][4 * FH];
-    // region of wave w: its transpose scratch during a transform, then its
-    // partial products (output q, slot*64 + lane) at q*FH; region 2 ends up
-    // holding the six-row sums
-    __shared__ d2 region[LAT_WAVES][LAT_REGION];
+    // region of wave w: its transpose scratch during a transform, then (digit
+    // waves) its spectrum in (slot, lane) order
+    __shared__ d2 region[LAT_WAVES][SCR];
+    __shared__ d2 sums[2][FH];                 // output q's spectrum, (slot, lane) order
     const int tid = threadIdx.x, lane = tid & 63;
-    const int p = tid >> 6;                    // digit row of this wave: component c, digit jj
+    const int w = tid >> 6;
+    const bool digit_wave = w < 6;
+    const int p = digit_wave ? w : 0;          // digit row of a digit wave: component c, digit jj
     const int c = p / 3, jj = p - 3 * c;
     const uint32_t sh = (uint32_t)(32 - 7 * (jj + 1));
+    const int q_inv = w - 6;                   // output of an inverse wave (waves 6, 7)
     const int64_t g = blockIdx.x;              // the grid has exactly one workgroup per gate
-    d2 *scr = region[p];
+    d2 *scr = region[w];
     const uint16_t *bar = bars + g * (int64_t)(n + 1);
     const Tw t0 = make_tw(lane);
     Tw t = t0;
@@ -517,19 +525,19 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
         *reinterpret_cast<uint4 *>(&zacc[0][4 * e]) = uint4{0u, 0u, 0u, 0u};
         *reinterpret_cast<uint4 *>(&zacc[1][4 * e]) = uint4{r[0], r[1], tv((uint32_t)e), tv((uint32_t)(e + FH))};
     }
-    // the two output waves keep their component's own 16 coefficients
+    // the two inverse waves keep their component's own 16 coefficients
     // (j = lane + 64 m + 512 h) in registers
     uint32_t mine[16];
     static_for<0, 16>([&](auto sI) {
         constexpr int sl = decltype(sI)::value;
         const uint32_t tt = ((uint32_t)(lane + 64 * sl) + bb) & (uint32_t)(2 * FN - 1);
-        mine[sl] = p == 1 ? (tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u) : 0u;
+        mine[sl] = q_inv == 1 ? (tt < (uint32_t)FN ? 0x20000000u : 0xE0000000u) : 0u;
     });
-    // key spectra of (step 0, row p) for both outputs, in (q, slot, lane) order
-    d2 kq[16];
+    // key values of this wave's slot for step 0: kr[2 p + q] = K_{p,q}[slot w, lane]
+    d2 kr[12];
     {
-        const d2 *src = spec + (int64_t)p * STAGE_D2 + lane;
-        static_for<0, 16>([&](auto kI) { kq[decltype(kI)::value] = src[decltype(kI)::value * 64]; });
+        const d2 *src = spec + w * 64 + lane;
+        static_for<0, 12>([&](auto kI) { kr[decltype(kI)::value] = src[decltype(kI)::value * FH]; });
     }
     __syncthreads();
 
@@ -537,64 +545,61 @@ __global__ __launch_bounds__(64 * LAT_WAVES, 1) void br_fft_lat_kernel(const d2 
     for (int i = 0; i < n; ++i) {
         // the next step's rotation, applied when the ACC records are written back
         const uint32_t a_next = i + 1 < n ? (uint32_t)bar[i + 1] : 0u;
-        // waves 4 and 5 share a SIMD with waves 0 and 1, which the arbiter
-        // issues first; raising them until the first transpose of their
-        // forward transform lets each pair finish that phase together
-        if (p >= 4) __builtin_amdgcn_s_setprio(1);
         launder(t.tw); launder(t.f1); launder(t.f2); launder(t.i2c); launder(t.i2b);
-        // digit jj of D = X^a ACC_c - ACC_c at this lane's 16 coefficients
-        d2 x[8];
-        // all eight records requested before the first is used (left to
-        // itself the compiler keeps two reads in flight, exposing their latency)
-        uint4 zw[8];
-        static_for<0, 8>([&](auto mI) { zw[decltype(mI)::value] = zc[64 * decltype(mI)::value]; });
-        __builtin_amdgcn_sched_barrier(0);
-        static_for<0, 8>([&](auto mI) {
-            constexpr int m = decltype(mI)::value;
-            const uint4 w = zw[m];
-            const uint32_t d0 = w.x - w.z + kDigitOffset;
-            const uint32_t d1 = w.y - w.w + kDigitOffset;
-            const double lo = (double)((int32_t)((d0 >> sh) & 127u) - 64);
-            const double hi = (double)((int32_t)((d1 >> sh) & 127u) - 64);
-            x[m] = cmul(d2{lo, hi}, twist_slot(m));
-        });
-        __builtin_amdgcn_sched_barrier(0);
-        fft_fwd<true>(x, scr, lane, t);
-        __builtin_amdgcn_sched_barrier(0);
-        // partial products of this digit row with the two key spectra, into
-        // this wave's region (its transform is done; LDS ops of a wave are
-        // ordered)
-        wave_lds_fence();
-        static_for<0, 8>([&](auto sI) {
-            constexpr int sl = decltype(sI)::value;
-            scr[sl * 64 + lane] = cmul(x[sl], kq[sl]);
-            scr[FH + sl * 64 + lane] = cmul(x[sl], kq[8 + sl]);
-        });
-        {   // prefetch the next step's key spectra (past the last step: step 0, unused)
-            const int ni = i + 1 < n ? i + 1 : 0;
-            const d2 *src = spec + ((int64_t)ni * 6 + p) * STAGE_D2 + lane;
-            static_for<0, 16>([&](auto kI) { kq[decltype(kI)::value] = src[decltype(kI)::value * 64]; });
+        if (digit_wave) {
+            // waves 4 and 5 share a SIMD with waves 0 and 1, which the arbiter
+            // issues first; raising them until the first transpose of their
+            // forward transform lets each pair finish that phase together
+            if (p >= 4) __builtin_amdgcn_s_setprio(1);
+            // digit jj of D = X^a ACC_c - ACC_c at this lane's 16 coefficients
+            d2 x[8];
+            // all eight records requested before the first is used (left to
+            // itself the compiler keeps two reads in flight, exposing their latency)
+            uint4 zw[8];
+            static_for<0, 8>([&](auto mI) { zw[decltype(mI)::value] = zc[64 * decltype(mI)::value]; });
+            __builtin_amdgcn_sched_barrier(0);
+            static_for<0, 8>([&](auto mI) {
+                constexpr int m = decltype(mI)::value;
+                const uint4 zv = zw[m];
+                const uint32_t d0 = zv.x - zv.z + kDigitOffset;
+                const uint32_t d1 = zv.y - zv.w + kDigitOffset;
+                const double lo = (double)((int32_t)((d0 >> sh) & 127u) - 64);
+                const double hi = (double)((int32_t)((d1 >> sh) & 127u) - 64);
+                x[m] = cmul(d2{lo, hi}, twist_slot(m));
+            });
+            __builtin_amdgcn_sched_barrier(0);
+            fft_fwd<true>(x, scr, lane, t);
+            __builtin_amdgcn_sched_barrier(0);
+            // the spectrum, into this wave's region (its transform is done;
+            // LDS ops of a wave are ordered)
+            wave_lds_fence();
+            static_for<0, 8>([&](auto sI) { scr[decltype(sI)::value * 64 + lane] = x[decltype(sI)::value]; });
         }
-        __syncthreads();   // partial products visible
-        // the six rows summed in row order, (output, slot) pairs spread over
-        // the six waves (pairs p, p + 6, p + 12); the sum replaces row 2's
-        // term in place
-#pragma unroll
-        for (int k = p; k < 2 * 8; k += LAT_WAVES) {
-            const int e = (k >> 3) * FH + (k & 7) * 64 + lane;
-            d2 v = region[0][e] + region[1][e];
-#pragma unroll
-            for (int w = 2; w < LAT_WAVES; ++w) v += region[w][e];
-            region[2][e] = v;
+        __syncthreads();   // spectra visible
+        {
+            // slot w of both outputs: the six rows in row order
+            d2 sa = d2{0.0, 0.0}, sb = d2{0.0, 0.0};
+            static_for<0, 6>([&](auto rI) {
+                constexpr int r = decltype(rI)::value;
+                const d2 xr = region[r][w * 64 + lane];
+                sa = cmac(sa, xr, kr[2 * r]);
+                sb = cmac(sb, xr, kr[2 * r + 1]);
+            });
+            sums[0][w * 64 + lane] = sa;
+            sums[1][w * 64 + lane] = sb;
+            // the next step's key values (past the last step: step 0, unused)
+            const int ni = i + 1 < n ? i + 1 : 0;
+            const d2 *src = spec + (int64_t)ni * 6 * STAGE_D2 + w * 64 + lane;
+            static_for<0, 12>([&](auto kI) { kr[decltype(kI)::value] = src[decltype(kI)::value * FH]; });
         }
         __syncthreads();   // sums visible
-        if (p < 2) {
-            // output q = p: inverse transform, untwist, round and accumulate
-            // into ACC_q (scratch: this wave's own region, consumed above)
+        if (!digit_wave) {
+            // output q: inverse transform, untwist, round and accumulate into
+            // ACC_q (scratch: this wave's own region)
             d2 y[8];
-            static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] = region[2][p * FH + decltype(sI)::value * 64 + lane]; });
+            static_for<0, 8>([&](auto sI) { y[decltype(sI)::value] = sums[q_inv][decltype(sI)::value * 64 + lane]; });
             fft_inv(y, scr, lane, t);
-            uint32_t *zq = zacc[p];
+            uint32_t *zq = zacc[q_inv];
             static_for<0, 8>([&](auto mI) {
                 constexpr int m = decltype(mI)::value;
                 const d2 z = cmul(y[m], cconj(twist_slot(m)));
