@@ -565,20 +565,23 @@ __device__ __forceinline__ void lat_mfma_block(const uint32_t *__restrict__ pr, 
                                                const v4i (&bf)[LatShape<N, WAVES>::KT])
 {
     using S = LatShape<N, WAVES>;
-    // Software pipeline: fragment di + 1 is requested before the MFMAs of
-    // fragment di are issued; sched_barrier keeps that order.
-    v4i fr = v4i{(int)pr[0], (int)pr[1], (int)pr[2], (int)pr[3]};
+    // Software pipeline: fragment di + 2 is requested before the MFMAs of
+    // fragment di are issued (with one wave per SIMD, one fragment of MFMAs
+    // does not cover a read's latency); sched_barrier keeps that order.
+    auto frag = [&](int di) { return v4i{(int)pr[4 * di], (int)pr[4 * di + 1], (int)pr[4 * di + 2], (int)pr[4 * di + 3]}; };
+    v4i fr = frag(0);
+    v4i f1 = S::NDELTA > 1 ? frag(1) : fr;
     static_for<0, S::NDELTA>([&](auto dI) {
         constexpr int di = decltype(dI)::value;
-        v4i nx = fr;
-        if constexpr (di + 1 < S::NDELTA)
-            nx = v4i{(int)pr[4 * di + 4], (int)pr[4 * di + 5], (int)pr[4 * di + 6], (int)pr[4 * di + 7]};
+        v4i f2 = f1;
+        if constexpr (di + 2 < S::NDELTA) f2 = frag(di + 2);
         static_for<0, S::KT>([&](auto bI) {
             constexpr int b = decltype(bI)::value;
             constexpr int a = di - 4 * (S::KT - 1) + 4 * b;
             if constexpr (a >= 0 && a < S::MT) acc[a] = __builtin_amdgcn_mfma_i32_16x16x64_i8(fr, bf[b], acc[a], 0, 0, 0);
         });
-        fr = nx;
+        fr = f1;
+        f1 = f2;
         __builtin_amdgcn_sched_barrier(0);
     });
 }
