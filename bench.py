@@ -66,8 +66,8 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 TRAFFIC = {
     "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "164437d8265df2ca",
               "bytes": 486_912 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
-    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "e499637829b4daae",
-             "bytes": 246_001 * 1024 * 2 + 18_960 * 1024, "batch": 4096},
+    "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "709541717732388d",
+             "bytes": 246_002 * 1024 * 2 + 18_960 * 1024, "batch": 4096},
     # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
     "ks": {"source": "paper_2101_03403_amd/csrc/cemu_ks.hip", "sha256_16": "8f9eb8b89663227d",
            "bytes": (274 + 383_248) * 1024 * 2 + (10_096 + 29_152) * 1024, "batch": 4096},
