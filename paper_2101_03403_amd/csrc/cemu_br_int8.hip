@@ -283,9 +283,10 @@ __global__ __launch_bounds__(64 * WAVES, 1) void br_int8_kernel(const uint8_t *_
 // alignment; and it depends on b - u only, so one fragment serves every
 // (u, b) pair on that diagonal: 256 MFMAs per 31 fragments (N = 1024)
 // against 76 with blocks of consecutive rows. The columns shifted past N
-// wrap around: column N + k' (k' < c <= v <= m) meets R[2N - 1 - m + k'] =
-// -T[m][k'], so it is fed the negated digit -d[k'] (digits are in [-64, 64),
-// so their negations fit a signed byte).
+// wrap around: column N + k' (k' < c = v + 1, so k' <= v <= m; for v = 3
+// nothing wraps) meets R[2N - 1 - m + k'] = -T[m][k'], so it is fed the
+// negated digit -d[k'] (digits are in [-64, 64), so their negations fit a
+// signed byte).
 //
 // ACC row m of a gate is kept at the permuted position
 //   P(m) = (m & ~15) | ((m & 3) << 2) | ((m >> 2) & 3)
