@@ -107,8 +107,9 @@ int cemu_params_default(cemu_params *p, int which);
  * random value is a Philox4x32-10 output at a fixed counter, keyed by seed,
  * so the same seed gives the same keys on any machine. The secret key stays
  * on the host. The cloud key (bootstrapping key in the int8-limb layout and
- * the key-switching key) is uploaded to the current HIP device; the FFT form
- * of the bootstrapping key is built on that device on first use.
+ * the key-switching key) is uploaded to the current HIP device; for N = 1024
+ * the FFT form of the bootstrapping key is built there too, before the call
+ * returns, so that later gate calls need no set-up.
  * Ownership: *sk and *ck are owned by the library until cemu_free_*.
  * Errors: CEMU_ERR_NULL, CEMU_ERR_PARAM / CEMU_ERR_UNSUPPORTED (parameter set
  * outside the limits stated in cemu_params), CEMU_ERR_OOM, CEMU_ERR_HIP. */
@@ -298,8 +299,9 @@ void cemu_free_cloud_key(cemu_cloud_key *ck);
  *   GPU (the key limbs fill the columns instead). 0 selects 16.
  * fft_gates_per_wg: gates per workgroup of the FFT64 kernel, 4 (one wave per
  *   SIMD, 512 registers each) or 8 (two waves per SIMD; default), or 1: the
- *   latency kernel, one gate per workgroup of 6 waves (one wave per gadget
- *   digit row), for batches too narrow to fill the GPU.
+ *   latency kernel, one gate per workgroup of 8 waves (six run the forward
+ *   transforms of the six gadget digit rows, two the inverse transforms), for
+ *   batches too narrow to fill the GPU.
  * The int8 choices and FFT64 choices 4/8 only change speed, never results.
  * FFT64 choice 1 adds the six digit-row products in another rounding order;
  * since every product is an integer polynomial, all FFT64 choices return the

@@ -31,7 +31,7 @@ struct cemu_cloud_key {
     // The same key as int8 limbs in MFMA B-operand order (see cemu_ks.hip),
     // present when the parameters allow the MFMA key switch (t = 8).
     uint8_t *d_ksk_mfma = nullptr;
-    // Bootstrapping key in the FFT form (built on first use): for step i and
+    // Bootstrapping key in the FFT form (built at key generation, N = 1024): for step i and
     // row r, component q, the twisted spectrum of the centred key polynomial,
     // [n][2l][2][N/2] complex doubles stored as (re, im).
     double *d_bkfft = nullptr;
