@@ -90,9 +90,9 @@ typedef struct cemu_params {
     int32_t t;         /* key-switching length: 1..16, t*basebit <= 32       */
     int32_t basebit;   /* key-switching base bits: must be 2                  */
     int32_t reserved;  /* set to 0                                           */
-    double sigma_lwe;  /* std dev of fresh LWE noise, torus units (>= 0)     */
-    double sigma_ks;   /* std dev of key-switching-key noise                 */
-    double sigma_bk;   /* std dev of bootstrapping-key noise                 */
+    double sigma_lwe;  /* std dev of fresh LWE noise, torus units, in [0, 1] */
+    double sigma_ks;   /* std dev of key-switching-key noise, same range     */
+    double sigma_bk;   /* std dev of bootstrapping-key noise, same range     */
 } cemu_params;
 
 typedef struct cemu_secret_key cemu_secret_key;

@@ -58,8 +58,11 @@ int check_params(const cemu_params *p)
         return fail(CEMU_ERR_UNSUPPORTED, "the kernels need l = 3 and Bgbit = 7 (signed 7-bit digits)");
     if (p->basebit != 2) return fail(CEMU_ERR_UNSUPPORTED, "key switching needs basebit = 2");
     if (p->t < 1 || p->t * p->basebit > 32) return fail(CEMU_ERR_PARAM, "t must satisfy 1 <= t, t*basebit <= 32");
-    if (!(p->sigma_lwe >= 0.0) || !(p->sigma_ks >= 0.0) || !(p->sigma_bk >= 0.0))
-        return fail(CEMU_ERR_PARAM, "noise deviations must be >= 0");
+    // a deviation of a whole torus period or more (or NaN, or infinity) has
+    // no meaning, and its samples would overflow the rounding to an integer
+    auto ok_sigma = [](double s) { return s >= 0.0 && s <= 1.0; };
+    if (!ok_sigma(p->sigma_lwe) || !ok_sigma(p->sigma_ks) || !ok_sigma(p->sigma_bk))
+        return fail(CEMU_ERR_PARAM, "noise deviations must be in [0, 1] (torus units)");
     return CEMU_OK;
 }
 

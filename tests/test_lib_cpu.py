@@ -41,7 +41,8 @@ def test_params_default():
 
 @pytest.mark.parametrize("field,value,code", [("N", 2048, -6), ("l", 4, -6), ("bgbit", 8, -6), ("k", 2, -6),
                                               ("basebit", 3, -6), ("t", 17, -1), ("n", 0, -1), ("n", 768, -6), ("n", 4097, -1),
-                                              ("sigma_bk", -1.0, -1)])
+                                              ("sigma_bk", -1.0, -1), ("sigma_lwe", float("inf"), -1),
+                                              ("sigma_ks", float("nan"), -1), ("sigma_bk", 2.0, -1)])
 def test_keygen_rejects_unsupported_params_before_touching_the_gpu(field, value, code):
     p = cemu.params(cemu.STD, **{field: value})
     sk, ck = C.c_void_p(), C.c_void_p()
