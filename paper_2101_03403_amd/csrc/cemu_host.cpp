@@ -27,6 +27,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <thread>
 
@@ -123,6 +126,9 @@ enum : uint32_t {
     kDomKsMask = 5, kDomKsNoise = 6, kDomEncMask = 7, kDomEncNoise = 8
 };
 
+// Runs f(0 .. count-1) over the host's threads. An exception thrown by f is
+// rethrown in the caller once every worker has stopped; slices for which no
+// thread could be started run on the calling thread.
 template <class F>
 void parallel_for(int64_t count, F &&f)
 {
@@ -133,13 +139,42 @@ void parallel_for(int64_t count, F &&f)
         for (int64_t i = 0; i < count; ++i) f(i);
         return;
     }
-    std::vector<std::thread> th;
-    th.reserve((size_t)nt);
-    for (int64_t w = 0; w < nt; ++w)
-        th.emplace_back([&, w] {
+    std::exception_ptr err;
+    std::mutex err_mu;
+    auto slice = [&](int64_t w) {
+        try {
             for (int64_t i = w; i < count; i += nt) f(i);
-        });
+        } catch (...) {
+            std::lock_guard<std::mutex> g(err_mu);
+            if (!err) err = std::current_exception();
+        }
+    };
+    std::vector<std::thread> th;
+    int64_t w = 0;
+    try {
+        th.reserve((size_t)nt);
+        for (; w < nt; ++w) th.emplace_back(slice, w);
+    } catch (...) {
+        for (; w < nt; ++w) slice(w);
+    }
     for (auto &x : th) x.join();
+    if (err) std::rethrow_exception(err);
+}
+
+// Runs the body of an entry point, turning a host exception (allocation
+// failure above all) into an error code, so that none crosses the C ABI.
+template <class F>
+int guarded(F &&body)
+{
+    try {
+        return body();
+    } catch (const std::bad_alloc &) {
+        return fail(CEMU_ERR_OOM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(CEMU_ERR_OOM, std::string("host error: ") + e.what());
+    } catch (...) {
+        return fail(CEMU_ERR_OOM, "host error");
+    }
 }
 
 // Signed balanced 8-bit limbs of a Torus32 value: x = sum_k 2^(8k) s_k mod 2^32,
@@ -215,119 +250,102 @@ int cemu_keygen(const cemu_params *p, uint64_t seed, cemu_secret_key **sk_out, c
     if (!sk_out || !ck_out) return fail(CEMU_ERR_NULL, "output handle pointer is NULL");
     *sk_out = nullptr;
     *ck_out = nullptr;
-    int rc = check_params(p);
+    const int rc = check_params(p);
     if (rc) return rc;
-    const int32_t n = p->n, N = p->N, l = p->l, t = p->t, base = 1 << p->basebit;
-    const Philox rng(seed);
+    return guarded([&]() -> int {
+        const int32_t n = p->n, N = p->N, l = p->l, t = p->t, base = 1 << p->basebit;
+        const Philox rng(seed);
 
-    cemu_secret_key *sk = new (std::nothrow) cemu_secret_key;
-    if (!sk) return fail(CEMU_ERR_OOM, "host allocation failed");
-    sk->p = *p;
-    try {
+        std::unique_ptr<cemu_secret_key> sk(new cemu_secret_key);
+        sk->p = *p;
         sk->lwe_key.resize((size_t)n);
         sk->tlwe_key.resize((size_t)N);
-    } catch (...) {
-        delete sk;
-        return fail(CEMU_ERR_OOM, "host allocation failed");
-    }
-    for (int32_t u = 0; u < n; ++u) sk->lwe_key[(size_t)u] = (int32_t)(rng.word((uint32_t)u, 0, 0, kDomLweKey) & 1u);
-    for (int32_t m = 0; m < N; ++m) sk->tlwe_key[(size_t)m] = (int32_t)(rng.word((uint32_t)m, 0, 0, kDomTlweKey) & 1u);
+        for (int32_t u = 0; u < n; ++u) sk->lwe_key[(size_t)u] = (int32_t)(rng.word((uint32_t)u, 0, 0, kDomLweKey) & 1u);
+        for (int32_t m = 0; m < N; ++m) sk->tlwe_key[(size_t)m] = (int32_t)(rng.word((uint32_t)m, 0, 0, kDomTlweKey) & 1u);
 
-    // Positions of the ones of S: A*S is the sum of X^k * A over them.
-    std::vector<int32_t> ones;
-    for (int32_t m = 0; m < N; ++m)
-        if (sk->tlwe_key[(size_t)m]) ones.push_back(m);
-
-    const size_t rbytes = (size_t)2 * N;
-    std::vector<uint8_t> bk8;
-    std::vector<uint32_t> ksk;
-    try {
-        bk8.resize((size_t)n * 2 * l * 2 * 4 * rbytes);
-        ksk.resize((size_t)N * t * base * (n + 1));
-    } catch (...) {
-        delete sk;
-        return fail(CEMU_ERR_OOM, "host allocation failed");
-    }
-
-    // TRGSW rows: one task per (i, r).
-    parallel_for((int64_t)n * 2 * l, [&](int64_t task) {
-        const int32_t i = (int32_t)(task / (2 * l)), r = (int32_t)(task % (2 * l));
-        std::vector<uint32_t> A((size_t)N), B((size_t)N, 0u);
-        for (int32_t m = 0; m < N; ++m) A[(size_t)m] = rng.word((uint32_t)m, (uint32_t)r, (uint32_t)i, kDomBkMask);
-        for (int32_t k : ones) {          // B += X^k * A
-            for (int32_t m = 0; m < N; ++m) {
-                const int32_t src = m - k;
-                B[(size_t)m] += src >= 0 ? A[(size_t)src] : 0u - A[(size_t)(src + N)];
-            }
-        }
+        // Positions of the ones of S: A*S is the sum of X^k * A over them.
+        std::vector<int32_t> ones;
         for (int32_t m = 0; m < N; ++m)
-            B[(size_t)m] += rng.gauss((uint32_t)m, (uint32_t)r, (uint32_t)i, kDomBkNoise, p->sigma_bk);
-        const int32_t c = r / l, j = r % l;
-        if (sk->lwe_key[(size_t)i]) {
-            const uint32_t h = 1u << (32 - (j + 1) * p->bgbit);
-            if (c == 0) A[0] += h; else B[0] += h;
-        }
-        // int8-limb layout of both components
-        for (int q = 0; q < 2; ++q) {
-            const std::vector<uint32_t> &P = q == 0 ? A : B;
-            uint8_t *dst = bk8.data() + (((size_t)i * 2 * l + r) * 2 + q) * 4 * rbytes;
-            for (int32_t u = 0; u < 2 * N; ++u) {
-                const int32_t e = 2 * N - 1 - u;  // index into the extended sequence
-                const uint32_t val = e >= N ? P[(size_t)(e - N)] : 0u - P[(size_t)e];
-                int8_t s[4];
-                limbs4(val, s);
-                for (int kk = 0; kk < 4; ++kk) dst[(size_t)kk * rbytes + (size_t)u] = (uint8_t)s[kk];
-            }
-        }
-    });
+            if (sk->tlwe_key[(size_t)m]) ones.push_back(m);
 
-    // Key-switching key: one task per (i, j).
-    parallel_for((int64_t)N * t, [&](int64_t task) {
-        const int32_t i = (int32_t)(task / t), j = (int32_t)(task % t);
-        for (int32_t v = 0; v < base; ++v) {
-            uint32_t *row = ksk.data() + (((size_t)i * t + j) * base + v) * (size_t)(n + 1);
-            const uint32_t c1 = (uint32_t)(j * base + v);
-            uint32_t body = 0;
-            for (int32_t u = 0; u < n; ++u) {
-                const uint32_t a = rng.word((uint32_t)u, c1, (uint32_t)i, kDomKsMask);
-                row[u] = a;
-                if (sk->lwe_key[(size_t)u]) body += a;
+        const size_t rbytes = (size_t)2 * N;
+        std::vector<uint8_t> bk8((size_t)n * 2 * l * 2 * 4 * rbytes);
+        std::vector<uint32_t> ksk((size_t)N * t * base * (n + 1));
+        // TRGSW rows: one task per (i, r).
+        parallel_for((int64_t)n * 2 * l, [&](int64_t task) {
+            const int32_t i = (int32_t)(task / (2 * l)), r = (int32_t)(task % (2 * l));
+            std::vector<uint32_t> A((size_t)N), B((size_t)N, 0u);
+            for (int32_t m = 0; m < N; ++m) A[(size_t)m] = rng.word((uint32_t)m, (uint32_t)r, (uint32_t)i, kDomBkMask);
+            for (int32_t k : ones) {          // B += X^k * A
+                for (int32_t m = 0; m < N; ++m) {
+                    const int32_t src = m - k;
+                    B[(size_t)m] += src >= 0 ? A[(size_t)src] : 0u - A[(size_t)(src + N)];
+                }
             }
-            const int32_t sh = 32 - (j + 1) * p->basebit;
-            const uint32_t mu = sh >= 32 ? 0u : ((uint32_t)(v * sk->tlwe_key[(size_t)i]) << sh);
-            row[n] = body + mu + rng.gauss(0, c1, (uint32_t)i, kDomKsNoise, p->sigma_ks);
-        }
-    });
-
-    std::vector<uint8_t> ksk_mfma;
-    if (ks_mfma_supported(*p)) {
-        try {
-            ksk_mfma.resize(ks_mfma_bytes(*p));
-        } catch (...) {
-            delete sk;
-            return fail(CEMU_ERR_OOM, "host allocation failed");
-        }
-        const int ntiles = ks_mfma_ntiles(*p);
-        parallel_for((int64_t)4 * ntiles, [&](int64_t task) {
-            ks_mfma_arrange(*p, ksk.data(), ksk_mfma.data(), (int)(task / ntiles), (int)(task % ntiles));
+            for (int32_t m = 0; m < N; ++m)
+                B[(size_t)m] += rng.gauss((uint32_t)m, (uint32_t)r, (uint32_t)i, kDomBkNoise, p->sigma_bk);
+            const int32_t c = r / l, j = r % l;
+            if (sk->lwe_key[(size_t)i]) {
+                const uint32_t h = 1u << (32 - (j + 1) * p->bgbit);
+                if (c == 0) A[0] += h; else B[0] += h;
+            }
+            // int8-limb layout of both components
+            for (int q = 0; q < 2; ++q) {
+                const std::vector<uint32_t> &P = q == 0 ? A : B;
+                uint8_t *dst = bk8.data() + (((size_t)i * 2 * l + r) * 2 + q) * 4 * rbytes;
+                for (int32_t u = 0; u < 2 * N; ++u) {
+                    const int32_t e = 2 * N - 1 - u;  // index into the extended sequence
+                    const uint32_t val = e >= N ? P[(size_t)(e - N)] : 0u - P[(size_t)e];
+                    int8_t s[4];
+                    limbs4(val, s);
+                    for (int kk = 0; kk < 4; ++kk) dst[(size_t)kk * rbytes + (size_t)u] = (uint8_t)s[kk];
+                }
+            }
         });
-    }
 
-    cemu_cloud_key *ck = new (std::nothrow) cemu_cloud_key;
-    if (!ck) {
-        delete sk;
-        return fail(CEMU_ERR_OOM, "host allocation failed");
-    }
-    ck->p = *p;
-    rc = upload_cloud_key(ck, bk8, ksk, ksk_mfma);
-    if (rc) {
-        delete ck;
-        delete sk;
-        return rc;
-    }
-    *sk_out = sk;
-    *ck_out = ck;
-    return CEMU_OK;
+        // Key-switching key: one task per (i, j).
+        parallel_for((int64_t)N * t, [&](int64_t task) {
+            const int32_t i = (int32_t)(task / t), j = (int32_t)(task % t);
+            for (int32_t v = 0; v < base; ++v) {
+                uint32_t *row = ksk.data() + (((size_t)i * t + j) * base + v) * (size_t)(n + 1);
+                const uint32_t c1 = (uint32_t)(j * base + v);
+                uint32_t body = 0;
+                for (int32_t u = 0; u < n; ++u) {
+                    const uint32_t a = rng.word((uint32_t)u, c1, (uint32_t)i, kDomKsMask);
+                    row[u] = a;
+                    if (sk->lwe_key[(size_t)u]) body += a;
+                }
+                const int32_t sh = 32 - (j + 1) * p->basebit;
+                const uint32_t mu = sh >= 32 ? 0u : ((uint32_t)(v * sk->tlwe_key[(size_t)i]) << sh);
+                row[n] = body + mu + rng.gauss(0, c1, (uint32_t)i, kDomKsNoise, p->sigma_ks);
+            }
+        });
+
+        std::vector<uint8_t> ksk_mfma;
+        if (ks_mfma_supported(*p)) {
+            ksk_mfma.resize(ks_mfma_bytes(*p));
+            const int ntiles = ks_mfma_ntiles(*p);
+            parallel_for((int64_t)4 * ntiles, [&](int64_t task) {
+                ks_mfma_arrange(*p, ksk.data(), ksk_mfma.data(), (int)(task / ntiles), (int)(task % ntiles));
+            });
+        }
+
+        // device buffers are released with the handle on every failure path
+        struct CloudDel {
+            void operator()(cemu_cloud_key *c) const
+            {
+                release_cloud_key(c);
+                delete c;
+            }
+        };
+        std::unique_ptr<cemu_cloud_key, CloudDel> ck(new cemu_cloud_key);
+        ck->p = *p;
+        const int up = upload_cloud_key(ck.get(), bk8, ksk, ksk_mfma);
+        if (up) return up;
+        *sk_out = sk.release();
+        *ck_out = ck.release();
+        return CEMU_OK;
+    });
 }
 
 int cemu_secret_params(const cemu_secret_key *sk, cemu_params *p)
@@ -354,12 +372,14 @@ int cemu_encrypt(const cemu_secret_key *sk, const uint8_t *bits, int64_t count, 
     if (count < 0) return fail(CEMU_ERR_RANGE, "count < 0");
     const Philox rng(seed);
     const int32_t n = sk->p.n;
-    parallel_for(count, [&](int64_t e) {
-        const uint32_t mu = bits[e] ? 0x20000000u : 0xE0000000u;
-        lwe_encrypt(sk->lwe_key.data(), n, rng, first_index + (uint64_t)e, mu, sk->p.sigma_lwe,
-                    out + (size_t)e * (size_t)(n + 1));
+    return guarded([&]() -> int {
+        parallel_for(count, [&](int64_t e) {
+            const uint32_t mu = bits[e] ? 0x20000000u : 0xE0000000u;
+            lwe_encrypt(sk->lwe_key.data(), n, rng, first_index + (uint64_t)e, mu, sk->p.sigma_lwe,
+                        out + (size_t)e * (size_t)(n + 1));
+        });
+        return CEMU_OK;
     });
-    return CEMU_OK;
 }
 
 int cemu_phase(const cemu_secret_key *sk, int extracted, const uint32_t *ct, int64_t count, uint32_t *phase)
@@ -401,35 +421,37 @@ int cemu_export_keys(const cemu_secret_key *sk, const cemu_cloud_key *ck, int32_
     clear_error();
     if ((lwe_key || tlwe_key) && !sk) return fail(CEMU_ERR_NULL, "secret key is NULL");
     if ((bk || ksk) && !ck) return fail(CEMU_ERR_NULL, "cloud key is NULL");
-    if (lwe_key) std::memcpy(lwe_key, sk->lwe_key.data(), sk->lwe_key.size() * sizeof(int32_t));
-    if (tlwe_key) std::memcpy(tlwe_key, sk->tlwe_key.data(), sk->tlwe_key.size() * sizeof(int32_t));
-    if (bk) {
-        std::vector<uint8_t> bk8;
-        int rc = download_bk8(ck, bk8);
-        if (rc) return rc;
-        const int32_t n = ck->p.n, N = ck->p.N, l = ck->p.l;
-        const size_t rbytes = (size_t)2 * N;
-        for (int32_t i = 0; i < n; ++i)
-            for (int32_t r = 0; r < 2 * l; ++r)
-                for (int q = 0; q < 2; ++q) {
-                    const uint8_t *src = bk8.data() + (((size_t)i * 2 * l + r) * 2 + q) * 4 * rbytes;
-                    uint32_t *dst = bk + (((size_t)i * 2 * l + r) * 2 + q) * (size_t)N;
-                    for (int32_t m = 0; m < N; ++m) {
-                        // BK[m] sits at extended index N + m, i.e. u = N - 1 - m
-                        const size_t u = (size_t)(N - 1 - m);
-                        int8_t s[4];
-                        for (int kk = 0; kk < 4; ++kk) s[kk] = (int8_t)src[(size_t)kk * rbytes + u];
-                        dst[m] = unlimbs4(s);
+    return guarded([&]() -> int {
+        if (lwe_key) std::memcpy(lwe_key, sk->lwe_key.data(), sk->lwe_key.size() * sizeof(int32_t));
+        if (tlwe_key) std::memcpy(tlwe_key, sk->tlwe_key.data(), sk->tlwe_key.size() * sizeof(int32_t));
+        if (bk) {
+            std::vector<uint8_t> bk8;
+            int rc = download_bk8(ck, bk8);
+            if (rc) return rc;
+            const int32_t n = ck->p.n, N = ck->p.N, l = ck->p.l;
+            const size_t rbytes = (size_t)2 * N;
+            for (int32_t i = 0; i < n; ++i)
+                for (int32_t r = 0; r < 2 * l; ++r)
+                    for (int q = 0; q < 2; ++q) {
+                        const uint8_t *src = bk8.data() + (((size_t)i * 2 * l + r) * 2 + q) * 4 * rbytes;
+                        uint32_t *dst = bk + (((size_t)i * 2 * l + r) * 2 + q) * (size_t)N;
+                        for (int32_t m = 0; m < N; ++m) {
+                            // BK[m] sits at extended index N + m, i.e. u = N - 1 - m
+                            const size_t u = (size_t)(N - 1 - m);
+                            int8_t s[4];
+                            for (int kk = 0; kk < 4; ++kk) s[kk] = (int8_t)src[(size_t)kk * rbytes + u];
+                            dst[m] = unlimbs4(s);
+                        }
                     }
-                }
-    }
-    if (ksk) {
-        std::vector<uint32_t> k;
-        int rc = download_ksk(ck, k);
-        if (rc) return rc;
-        std::memcpy(ksk, k.data(), k.size() * sizeof(uint32_t));
-    }
-    return CEMU_OK;
+        }
+        if (ksk) {
+            std::vector<uint32_t> k;
+            int rc = download_ksk(ck, k);
+            if (rc) return rc;
+            std::memcpy(ksk, k.data(), k.size() * sizeof(uint32_t));
+        }
+        return CEMU_OK;
+    });
 }
 
 void cemu_free_secret_key(cemu_secret_key *sk) { delete sk; }
