@@ -297,6 +297,13 @@ int ensure_workspace(cemu_cloud_key *ck, int64_t B, bool need_ext)
     return CEMU_OK;
 }
 
+// A launch that failed after prof_begin: drop its start event, report.
+int launch_failed(void *ev, const char *what, hipError_t e)
+{
+    if (ev) (void)hipEventDestroy((hipEvent_t)ev);
+    return fail(CEMU_ERR_HIP, hip_msg(what, e));
+}
+
 int log2_of(int v)
 {
     int r = 0;
@@ -311,7 +318,7 @@ int launch_lincomb(const cemu_cloud_key *ck, const uint8_t *ops, const uint32_t 
     void *ev = prof_begin(ck, s);
     hipLaunchKernelGGL(lincomb_modswitch_kernel, elem_grid(B * (n + 1)), dim3(kElemThreads), 0, s, ops, pool, ia, ib,
                        n, log2_of(2 * ck->p.N), B, bars);
-    CEMU_HIP(hipGetLastError());
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return launch_failed(ev, "lincomb launch", e);
     prof_end(ck, 0, s, ev);
     return CEMU_OK;
 }
@@ -335,7 +342,7 @@ int launch_key_switch(const cemu_cloud_key *ck, const uint32_t *ext, const int32
     else
         hipLaunchKernelGGL(key_switch_kernel<512>, dim3((unsigned)blocks), dim3(KS_THREADS), 0, s, ext, ck->d_ksk, n,
                            t, B, io, out);
-    CEMU_HIP(hipGetLastError());
+    if (const hipError_t e = hipGetLastError(); e != hipSuccess) return launch_failed(ev, "key switch launch", e);
     prof_end(ck, 3, s, ev);
     return CEMU_OK;
 }
@@ -393,7 +400,7 @@ int run_level(cemu_cloud_key *ck, int form, const uint32_t *pool, const uint8_t 
         void *ev = prof_begin(ck, s);
         hipLaunchKernelGGL(mux_lincomb_kernel, elem_grid(2 * M * (n + 1)), dim3(kElemThreads), 0, s, pool, ms, ma, mb,
                            n, log2_of(2 * N), M, ck->d_bars + G * (n + 1));
-        CEMU_HIP(hipGetLastError());
+        if (const hipError_t e = hipGetLastError(); e != hipSuccess) return launch_failed(ev, "MUX lincomb launch", e);
         prof_end(ck, 0, s, ev);
     }
     rc = run_br(ck, form, ck->d_bars, ck->d_ext, G + 2 * M, s);
