@@ -60,12 +60,13 @@ PEAK_HBM_BYTES = 8.0e12           # MI355X HBM3E, bytes/s
 # HBM bytes per launch of the blind-rotation kernels at B = 4096, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, scales from a
 # plain 1 GiB copy); summary and commands in profiles/. Valid only while the
-# kernel source's code is the one profiled (sha256 prefix of the source with
+# kernel's source code is the one profiled (sha256 prefix of the sources with
 # comments and whitespace removed, so that comment edits keep it), else
 # reported as null.
 TRAFFIC = {
-    "fft64": {"source": "paper_2101_03403_amd/csrc/cemu_br_fft.hip", "sha256_16": "164437d8265df2ca",
-              "bytes": 486_912 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
+    "fft64": {"source": ["paper_2101_03403_amd/csrc/cemu_br_fft.hip", "paper_2101_03403_amd/csrc/cemu_fft.h"],
+              "sha256_16": "1e1ade1190a8856e",
+              "bytes": 486_913 * 1024 * 2 + 16_400 * 1024, "batch": 4096},
     "int8": {"source": "paper_2101_03403_amd/csrc/cemu_br_int8.hip", "sha256_16": "709541717732388d",
              "bytes": 246_002 * 1024 * 2 + 18_960 * 1024, "batch": 4096},
     # the key switch of a 4096-gate batch: ks_init_kernel + ks_mfma_kernel<1024, true> (2 K splits)
@@ -74,20 +75,25 @@ TRAFFIC = {
 }
 
 
-def code_hash(path):
-    """sha256 prefix of a C/C++/HIP source with comments and whitespace removed."""
+def code_hash(paths):
+    """sha256 prefix of C/C++/HIP sources (one path or a list, in order) with
+    comments and whitespace removed."""
     import hashlib
     import re
-    text = open(path, encoding="utf-8").read()
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    return hashlib.sha256(" ".join(text.split()).encode()).hexdigest()[:16]
+    parts = []
+    for path in ([paths] if isinstance(paths, str) else paths):
+        text = open(path, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        parts.append(" ".join(text.split()))
+    return hashlib.sha256(" ".join(parts).encode()).hexdigest()[:16]
 
 
 def traffic_bytes(form, B):
     t = TRAFFIC[form]
     try:
-        h = code_hash(os.path.join(ROOT, t["source"]))
+        src = t["source"]
+        h = code_hash([os.path.join(ROOT, x) for x in src] if isinstance(src, list) else os.path.join(ROOT, src))
     except OSError:
         return None
     return t["bytes"] if (h == t["sha256_16"] and B == t["batch"]) else None

@@ -15,7 +15,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libcemu.so")
 
-HIP_SOURCES = ["cemu_device.hip", "cemu_br_int8.hip", "cemu_ks.hip", "cemu_br_fft.hip", "cemu_measure.hip"]
+HIP_SOURCES = ["cemu_device.hip", "cemu_br_int8.hip", "cemu_ks.hip", "cemu_br_fft.hip", "cemu_br_fft_lat.hip",
+               "cemu_measure.hip"]
+# per-file options: the FFT latency kernel runs faster with the machine
+# scheduler that forms the longest memory clauses (the others do not)
+HIP_FILE_FLAGS = {"cemu_br_fft_lat.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 HOST_SOURCES = ["cemu_host.cpp"]
 
 ARCH = "gfx950"
@@ -41,7 +45,7 @@ def build(verbose: bool = True) -> str:
         objs.append(obj)
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        _run([HIPCC, *HIP_FLAGS, *HIP_FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])

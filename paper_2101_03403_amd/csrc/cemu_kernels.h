@@ -17,6 +17,12 @@ int launch_br_fft(cemu_cloud_key *ck, const uint16_t *bars, int64_t B, uint32_t 
 // on stream s if it is not there yet; N = 1024 only.
 int build_bk_fft(cemu_cloud_key *ck, hipStream_t s);
 
+// One launch of the FFT latency kernel (one gate per workgroup of
+// 64 * LAT_WAVES threads) for cnt gates; spec is the key in the FFT form
+// (ck->d_bkfft). Errors are left to hipGetLastError.
+void launch_br_fft_lat(const double *spec, const uint16_t *bars, int32_t n, int64_t cnt, uint32_t *ext,
+                       hipStream_t s);
+
 // CEMU_OK if one launch of the key's current shape for the form holds B
 // blind rotations (a dispatch counts at most 2^32 - 1 work-items), else
 // CEMU_ERR_RANGE with the message set. The launchers check it too.
