@@ -6,7 +6,8 @@ by word in the test), so no oracle input comes from the GPU.
 * The throughput batch (4096 independent NAND/AND/OR/XOR gates, standard
   parameters) in the benchmark's launch shapes: every one of the 4096 int8
   outputs (extracted samples and key-switched ciphertexts) equals the
-  oracle's word for word, and so do the FFT64 form's. The FFT64 claim: each
+  oracle's word for word, and so do the FFT64 form's; the same for every
+  other launch shape of both forms. The FFT64 claim: each
   product is an integer polynomial computed in double precision, so while the
   transform error stays below one half every coefficient rounds to the exact
   integer and the extracted samples equal the exact ones; the maximum error
@@ -114,6 +115,17 @@ def truth(ops, a, b):
 
 
 # ------------------------------------------------------------------ the whole throughput batch
+# the launch shapes besides the benchmark's (int8: 16 gates per workgroup on
+# 8 waves; FFT64: 8 gates per workgroup)
+OTHER_SHAPES = [
+    ("fft64", {"fft_gates_per_wg": 4}),
+    ("fft64", {"fft_gates_per_wg": 1}),
+    ("int8", {"int8_waves": 4, "int8_gates_per_wg": 16}),
+    ("int8", {"int8_waves": 8, "int8_gates_per_wg": 1}),
+    ("int8", {"int8_waves": 4, "int8_gates_per_wg": 1}),
+]
+
+
 @pytest.fixture(scope="module")
 def batch4096(std, dev):
     lk, ok = std
@@ -128,6 +140,11 @@ def batch4096(std, dev):
         for form in ("int8", "fft64"):
             say(f"[gpu-full] {form} on {B} gates")
             res[form] = gpu_gates(lk, ops, c1, c2, dev, form)
+        # every other launch shape on the same batch
+        for form, tun in OTHER_SHAPES:
+            say(f"[gpu-full] {form} {tun} on {B} gates")
+            cemu.set_tuning(lk, **tun)
+            res[(form, tuple(sorted(tun.items())))] = gpu_gates(lk, ops, c1, c2, dev, form)
     finally:
         cemu.set_tuning(lk, **saved)
     say(f"[gpu-full] oracle on all {B} gates ({O.num_threads()} threads)")
@@ -154,6 +171,19 @@ def test_full_batch_fft64_words_equal(batch4096):
     (ext, out), (oext, oout) = res["fft64"], res["oracle"]
     assert word_report("fft64 extracted vs oracle", ext, oext) == 0
     assert word_report("fft64 output vs oracle", out, oout) == 0
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("form,tun", OTHER_SHAPES, ids=[f"{f}-{'-'.join(f'{k}{v}' for k, v in t.items())}" for f, t in OTHER_SHAPES])
+def test_full_batch_every_launch_shape(batch4096, form, tun):
+    """The other launch shapes (the FFT64 form at 4 gates per workgroup and
+    its one-gate latency kernel; the int8 form on 4 waves and its one-gate
+    latency kernel on 8 and 4 waves) give the oracle's words for all 4096
+    gates too."""
+    _, _, _, res = batch4096
+    (ext, out), (oext, oout) = res[(form, tuple(sorted(tun.items())))], res["oracle"]
+    assert word_report(f"{form} {tun} extracted vs oracle", ext, oext) == 0
+    assert word_report(f"{form} {tun} output vs oracle", out, oout) == 0
 
 
 @pytest.mark.timeout(900)
